@@ -1,0 +1,135 @@
+// Shared device helpers for the gfx950 kernels of the dense direct solvers.
+// Wave64 reductions, MFMA fragment types, the flag+payload ("low-latency")
+// message words used for cross-workgroup exchange, and launch checks.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace cds {
+
+constexpr int kWave = 64;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------
+// Device error word (bounded spins that time out record here; never hang).
+// ---------------------------------------------------------------------------
+enum DevErr : int { kErrNone = 0, kErrSpinTimeout = 1 };
+
+// ~ several seconds of polling; a correct run never comes close.
+constexpr long long kSpinLimit = 1ll << 23;
+
+// ---------------------------------------------------------------------------
+// Flag+payload words: a 64-bit word holds 32 bits of payload in the low half
+// and a 32-bit flag in the high half.  Written and read with agent-scope
+// relaxed atomics, which keep them coherent across the XCDs' separate L2
+// caches without a full cache write-back.  A reader spins until the flag it
+// expects appears, so each word validates itself and no fence is needed.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void ll_store(uint64_t* p, uint32_t payload, uint32_t flag) {
+  uint64_t w = ((uint64_t)flag << 32) | (uint64_t)payload;
+  __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Spin until the word's flag equals `flag`; returns the payload.  On time-out
+// records kErrSpinTimeout in *err and returns 0 (results are then invalid but
+// the kernel still terminates).
+__device__ __forceinline__ uint32_t ll_load(const uint64_t* p, uint32_t flag, int* err) {
+  long long spins = 0;
+  while (true) {
+    uint64_t w = __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(w >> 32) == flag) return (uint32_t)w;
+    ++spins;
+    if ((spins & 4095) == 0) {
+      // give up at once if another wait has already timed out
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return 0u;
+      if (spins > kSpinLimit) {
+        atomicExch(err, (int)kErrSpinTimeout);
+        return 0u;
+      }
+    }
+  }
+}
+
+// A double travels as two words (low and high halves).
+__device__ __forceinline__ void ll_store_f64(uint64_t* p, double v, uint32_t flag) {
+  uint64_t bits = __double_as_longlong(v);
+  ll_store(p, (uint32_t)bits, flag);
+  ll_store(p + 1, (uint32_t)(bits >> 32), flag);
+}
+__device__ __forceinline__ double ll_load_f64(const uint64_t* p, uint32_t flag, int* err) {
+  uint64_t lo = ll_load(p, flag, err);
+  uint64_t hi = ll_load(p + 1, flag, err);
+  return __longlong_as_double((long long)((hi << 32) | lo));
+}
+__device__ __forceinline__ void ll_store_val(uint64_t* p, double v, uint32_t flag) { ll_store_f64(p, v, flag); }
+__device__ __forceinline__ void ll_store_val(uint64_t* p, float v, uint32_t flag) {
+  ll_store(p, __float_as_uint(v), flag);
+}
+template <typename T> __device__ __forceinline__ T ll_load_val(const uint64_t* p, uint32_t flag, int* err);
+template <> __device__ __forceinline__ double ll_load_val<double>(const uint64_t* p, uint32_t flag, int* err) {
+  return ll_load_f64(p, flag, err);
+}
+template <> __device__ __forceinline__ float ll_load_val<float>(const uint64_t* p, uint32_t flag, int* err) {
+  return __uint_as_float(ll_load(p, flag, err));
+}
+// words per value in a message
+template <typename T> struct LLWords { static constexpr int n = 2; };
+template <> struct LLWords<float> { static constexpr int n = 1; };
+
+// ---------------------------------------------------------------------------
+// Wave-level helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+template <typename T>
+__device__ __forceinline__ T shfl_xor(T v, int m) { return __shfl_xor(v, m, kWave); }
+
+// (|v|, row) arg-max over the wave: larger magnitude wins, ties go to the lower
+// row index.  Invalid entries carry mag = -1.
+template <typename T>
+__device__ __forceinline__ void wave_argmax(T& mag, int& row) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    T om = shfl_xor(mag, m);
+    int orow = shfl_xor(row, m);
+    bool take = (om > mag) || (om == mag && orow < row);
+    mag = take ? om : mag;
+    row = take ? orow : row;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = fmax(v, shfl_xor(v, m));
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += shfl_xor(v, m);
+  return v;
+}
+
+__device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// Orders LDS accesses between the lanes of one wave (lanes run in lockstep and
+// the LDS serves one wave's requests in order; this keeps the compiler from
+// moving accesses across the point).
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+}  // namespace cds
+
+#define CDS_HIP_CHECK(expr)                          \
+  do {                                               \
+    hipError_t _e = (expr);                          \
+    if (_e != hipSuccess) return CDS_HIP_ERROR;      \
+  } while (0)

@@ -1,0 +1,346 @@
+// Trailing-matrix update  C += alpha * A * op(B)  on MFMA (gfx950).
+//
+// This is the rank-k "delayed update" of blocked LU (A22 -= L21 U12) and, in
+// lower-tile mode, the symmetric update of blocked Cholesky (A22 -= L21 L21^T):
+// Sec. 2 of the paper, where k rank-1 updates are replaced by one rank-k update
+// (level-3 BLAS).  It carries ~all of the O(n^3) flops.
+//
+// Design: 256-thread workgroups (4 waves, 2 x 2), a 128 x 128 C tile per
+// workgroup, 64 x 64 per wave = 4 x 4 MFMA 16x16 blocks held in accumulators.
+// A and B tiles are staged through LDS, double-buffered with a register
+// prefetch of the next K-slice.  FP64 uses v_mfma_f64_16x16x4, FP32
+// v_mfma_f32_16x16x4; the mixed variants read FP32 data, round it to BF16 or
+// FP16 while staging into LDS and use v_mfma_f32_16x16x32_{bf16,f16} with
+// FP32 accumulation.  Tiles are ordered so that consecutive workgroups on the
+// same XCD share the same A row-panel (XCD-aware block remapping).
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace cds {
+
+namespace {
+
+constexpr int BM = 128, BN = 128, NT = 256;
+
+template <typename T, int MODE> struct GemmCfg;
+// MODE 0: native precision MFMA
+template <> struct GemmCfg<double, 0> { static constexpr int BK = 16; };
+template <> struct GemmCfg<float, 0> { static constexpr int BK = 32; };
+// MODE 1: bf16 operands, MODE 2: fp16 operands (T = float storage)
+template <> struct GemmCfg<float, 1> { static constexpr int BK = 32; };
+template <> struct GemmCfg<float, 2> { static constexpr int BK = 32; };
+
+// Map a linear workgroup id to a (tile_m, tile_n) pair.
+// lower: enumerate tiles with tile_m >= tile_n only (m == n).
+__device__ __forceinline__ void tile_coords(int w, int tiles_m, int tiles_n, int lower, int& tm, int& tn) {
+  int total = lower ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
+  // XCD-aware remap: workgroup w runs on XCD (w % 8).  Give each XCD a
+  // contiguous range of tile ids so that its L2 sees neighbouring tiles.
+  int per = total / 8;
+  int t;
+  if (per > 0 && w < per * 8) {
+    t = (w % 8) * per + (w / 8);
+  } else {
+    t = w;
+  }
+  if (!lower) {
+    // column-major tile order inside the range: consecutive t share tile_n (B panel) and walk tile_m
+    tm = t % tiles_m;
+    tn = t / tiles_m;
+  } else {
+    // t -> (tm, tn) with tm >= tn, rows of the lower triangle of tiles
+    int r = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((r + 1) * (r + 2) / 2 <= t) ++r;
+    while (r * (r + 1) / 2 > t) --r;
+    tm = r;
+    tn = t - r * (r + 1) / 2;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T ldg_or_zero(const T* p, bool ok) { return ok ? *p : (T)0; }
+
+// ------------------------------------------------------------------------------------
+// Native-precision kernel (double: f64 MFMA; float: f32 MFMA)
+// ------------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(NT, 2)
+gemm_native_kernel(GemmArgs<T> g) {
+  if (g.guard && *g.guard != 0) return;
+  constexpr int BK = GemmCfg<T, 0>::BK;
+  constexpr int PADM = BM + 4;  // row pitch in LDS (elements)
+  __shared__ T As[2][BK][PADM];
+  __shared__ T Bs[2][BK][PADM];
+
+  const int b = blockIdx.y;
+  const T* __restrict__ A = g.A + (size_t)b * g.strideA;
+  const T* __restrict__ B = g.B + (size_t)b * g.strideB;
+  T* __restrict__ C = g.C + (size_t)b * g.strideC;
+
+  int tiles_m = (g.m + BM - 1) / BM, tiles_n = (g.n + BN - 1) / BN;
+  int tm, tn;
+  tile_coords(blockIdx.x, tiles_m, tiles_n, g.lower, tm, tn);
+  const int row0 = tm * BM, col0 = tn * BN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = (wave & 1) * 64, wc = (wave >> 1) * 64;
+
+  constexpr int A_PER = BM * BK / NT;  // elements per thread per tile
+  constexpr int B_PER = BK * BN / NT;
+  T ra[A_PER], rb[B_PER];
+
+  auto load_tile = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < A_PER; ++r) {
+      int e = tid + r * NT;
+      int i = e % BM, kk = e / BM;
+      int gi = row0 + i, gk = k0 + kk;
+      ra[r] = ldg_or_zero(A + gi + (size_t)gk * g.lda, gi < g.m && gk < g.k);
+    }
+    if (!g.transB) {
+#pragma unroll
+      for (int r = 0; r < B_PER; ++r) {
+        int e = tid + r * NT;
+        int kk = e % BK, j = e / BK;
+        int gk = k0 + kk, gj = col0 + j;
+        rb[r] = ldg_or_zero(B + gk + (size_t)gj * g.ldb, gk < g.k && gj < g.n);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < B_PER; ++r) {
+        int e = tid + r * NT;
+        int j = e % BN, kk = e / BN;
+        int gk = k0 + kk, gj = col0 + j;
+        rb[r] = ldg_or_zero(B + gj + (size_t)gk * g.ldb, gk < g.k && gj < g.n);
+      }
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < A_PER; ++r) {
+      int e = tid + r * NT;
+      As[buf][e / BM][e % BM] = ra[r];
+    }
+    if (!g.transB) {
+#pragma unroll
+      for (int r = 0; r < B_PER; ++r) {
+        int e = tid + r * NT;
+        Bs[buf][e % BK][e / BK] = rb[r];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < B_PER; ++r) {
+        int e = tid + r * NT;
+        Bs[buf][e / BN][e % BN] = rb[r];
+      }
+    }
+  };
+
+  typedef typename std::conditional<std::is_same<T, double>::value, d4, f4>::type acc_t;
+  acc_t acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = (acc_t){0, 0, 0, 0};
+
+  const int ktiles = (g.k + BK - 1) / BK;
+  load_tile(0);
+  store_tile(0);
+  __syncthreads();
+  for (int kt = 0; kt < ktiles; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < ktiles) load_tile((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      T af[4], bf[4];
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi) af[mi] = As[buf][kk + lane / 16][wr + mi * 16 + (lane & 15)];
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) bf[ni] = Bs[buf][kk + lane / 16][wc + ni * 16 + (lane & 15)];
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) {
+          if constexpr (std::is_same<T, double>::value)
+            acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
+          else
+            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
+        }
+    }
+    if (kt + 1 < ktiles) store_tile(buf ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: C += alpha * acc
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int r = std::is_same<T, double>::value ? (lane / 16 + 4 * v) : (4 * (lane / 16) + v);
+        int gi = row0 + wr + mi * 16 + r;
+        int gj = col0 + wc + ni * 16 + (lane & 15);
+        if (gi < g.m && gj < g.n && (!g.lower || gi >= gj)) {
+          T* p = C + gi + (size_t)gj * g.ldc;
+          *p = *p + g.alpha * acc[mi][ni][v];
+        }
+      }
+}
+
+// ------------------------------------------------------------------------------------
+// Mixed kernel: FP32 data, BF16 (MODE 1) or FP16 (MODE 2) operands, FP32 accumulate.
+// For FP16, op(B) is multiplied by 2^bscale_exp (device value) while staging and the
+// product by 2^-bscale_exp, both exact.
+// ------------------------------------------------------------------------------------
+template <int MODE>
+__global__ void __launch_bounds__(NT, 2)
+gemm_mixed_kernel(GemmArgs<float> g) {
+  if (g.guard && *g.guard != 0) return;
+  constexpr int BK = 32;
+  constexpr int PITCH = BK + 8;  // halfwords per LDS row (16 B aligned, skewed)
+  typedef typename std::conditional<MODE == 1, __bf16, _Float16>::type h_t;
+  typedef typename std::conditional<MODE == 1, bf16x8, f16x8>::type h8_t;
+  __shared__ __attribute__((aligned(16))) h_t As[2][BM][PITCH];
+  __shared__ __attribute__((aligned(16))) h_t Bs[2][BN][PITCH];
+
+  const int b = blockIdx.y;
+  const float* __restrict__ A = g.A + (size_t)b * g.strideA;
+  const float* __restrict__ B = g.B + (size_t)b * g.strideB;
+  float* __restrict__ C = g.C + (size_t)b * g.strideC;
+  float bscale = 1.0f, unscale = 1.0f;
+  if (MODE == 2 && g.scale_exp != nullptr) {
+    int e = g.scale_exp[b];
+    bscale = ldexpf(1.0f, e);
+    unscale = ldexpf(1.0f, -e);
+  }
+
+  int tiles_m = (g.m + BM - 1) / BM, tiles_n = (g.n + BN - 1) / BN;
+  int tm, tn;
+  tile_coords(blockIdx.x, tiles_m, tiles_n, g.lower, tm, tn);
+  const int row0 = tm * BM, col0 = tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave & 1) * 64, wc = (wave >> 1) * 64;
+
+  // each thread stages 2 units of 8 k-values for A and 2 for B
+  float ra[2][8], rb[2][8];
+  auto load_tile = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      int u = tid + r * NT;
+      int i = u % BM, kg = u / BM;
+      int gi = row0 + i;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        int gk = k0 + kg * 8 + t;
+        ra[r][t] = ldg_or_zero(A + gi + (size_t)gk * g.lda, gi < g.m && gk < g.k);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      int u = tid + r * NT;
+      int j, kg;
+      if (!g.transB) { kg = u % 4; j = u / 4; } else { j = u % BN; kg = u / BN; }
+      int gj = col0 + j;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        int gk = k0 + kg * 8 + t;
+        const float* p = g.transB ? (B + gj + (size_t)gk * g.ldb) : (B + gk + (size_t)gj * g.ldb);
+        rb[r][t] = ldg_or_zero(p, gk < g.k && gj < g.n);
+      }
+    }
+  };
+  auto store_tile = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      int u = tid + r * NT;
+      int i = u % BM, kg = u / BM;
+      h8_t v;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) v[t] = (h_t)ra[r][t];
+      *reinterpret_cast<h8_t*>(&As[buf][i][kg * 8]) = v;
+    }
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      int u = tid + r * NT;
+      int j, kg;
+      if (!g.transB) { kg = u % 4; j = u / 4; } else { j = u % BN; kg = u / BN; }
+      h8_t v;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) v[t] = (h_t)(rb[r][t] * bscale);
+      *reinterpret_cast<h8_t*>(&Bs[buf][j][kg * 8]) = v;
+    }
+  };
+
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = (f4){0, 0, 0, 0};
+
+  const int ktiles = (g.k + BK - 1) / BK;
+  load_tile(0);
+  store_tile(0);
+  __syncthreads();
+  for (int kt = 0; kt < ktiles; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < ktiles) load_tile((kt + 1) * BK);
+    h8_t af[4], bf[4];
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi) af[mi] = *reinterpret_cast<const h8_t*>(&As[buf][wr + mi * 16 + (lane & 15)][8 * (lane / 16)]);
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni) bf[ni] = *reinterpret_cast<const h8_t*>(&Bs[buf][wc + ni * 16 + (lane & 15)][8 * (lane / 16)]);
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) {
+        if constexpr (MODE == 1)
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
+        else
+          acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
+      }
+    if (kt + 1 < ktiles) store_tile(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int gi = row0 + wr + mi * 16 + 4 * (lane / 16) + v;
+        int gj = col0 + wc + ni * 16 + (lane & 15);
+        if (gi < g.m && gj < g.n && (!g.lower || gi >= gj)) {
+          float* p = C + gi + (size_t)gj * g.ldc;
+          *p = *p + g.alpha * (acc[mi][ni][v] * unscale);
+        }
+      }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_gemm(const GemmArgs<T>& g, int batch, int mode, hipStream_t s) {
+  if (g.m <= 0 || g.n <= 0 || g.k <= 0 || batch <= 0) return hipSuccess;
+  int tiles_m = (g.m + BM - 1) / BM, tiles_n = (g.n + BN - 1) / BN;
+  int tiles = g.lower ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
+  dim3 grid(tiles, batch);
+  if constexpr (std::is_same<T, double>::value) {
+    hipLaunchKernelGGL(gemm_native_kernel<double>, grid, dim3(NT), 0, s, g);
+  } else {
+    if (mode == 1)
+      hipLaunchKernelGGL(gemm_mixed_kernel<1>, grid, dim3(NT), 0, s, g);
+    else if (mode == 2)
+      hipLaunchKernelGGL(gemm_mixed_kernel<2>, grid, dim3(NT), 0, s, g);
+    else
+      hipLaunchKernelGGL(gemm_native_kernel<float>, grid, dim3(NT), 0, s, g);
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_gemm<double>(const GemmArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_gemm<float>(const GemmArgs<float>&, int, int, hipStream_t);
+
+}  // namespace cds

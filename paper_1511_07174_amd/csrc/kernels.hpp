@@ -1,0 +1,69 @@
+// Internal launch interfaces of the gfx950 kernels (not part of the C-ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+#include <type_traits>
+#include "../../include/cds.h"
+
+namespace cds {
+
+// C += alpha * A * op(B); A m x k, op(B) k x n, all column-major.
+// transB = 1: op(B) = B^T with B stored n x k (ldb).
+// lower = 1: only C(i, j) with i >= j is computed and written (m == n).
+// For the FP16 operand mode, scale_exp[b] (device, may be null) is the power of
+// two applied to op(B) before rounding; the product is scaled back.
+template <typename T>
+struct GemmArgs {
+  int m, n, k;
+  const T* A; int64_t lda; int64_t strideA;
+  const T* B; int64_t ldb; int64_t strideB;
+  T* C; int64_t ldc; int64_t strideC;
+  T alpha;
+  int transB;
+  int lower;
+  const int* scale_exp;
+  const int32_t* guard;   // optional: the launch does nothing when *guard != 0
+};
+// mode: 0 native MFMA of T, 1 bf16 operands (T = float), 2 fp16 operands (T = float)
+template <typename T>
+hipError_t launch_gemm(const GemmArgs<T>& g, int batch, int mode, hipStream_t s);
+
+// Execution context shared by the drivers.
+struct Ctx {
+  hipStream_t s0;          // caller's stream
+  hipStream_t s1;          // internal look-ahead stream
+  hipEvent_t ev[4];        // fork/join events
+  void* ws;                // workspace base (device)
+  size_t ws_bytes;
+  int* err;                // device error word (at the workspace base)
+  int nb_override;
+  int lookahead;
+  int leaf;
+  int panel_wgs;
+  int tune_getrf_nb_d, tune_getrf_nb_s, tune_potrf_nb_d, tune_potrf_nb_s;  // resolved per call
+};
+
+// Sizes of the workspace regions (bytes), shared by bufferSize queries and drivers.
+constexpr size_t kErrRegion = 256;
+size_t getrf_ws_bytes(int n, int nb, int leaf, int batch, size_t elem);
+size_t getrs_ws_bytes(int n, int nrhs, int batch, size_t elem);
+size_t potrf_ws_bytes(int n, int nb, size_t elem);
+
+template <typename T>
+cds_status_t getrf_run(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, int32_t* ipiv, int64_t strideP,
+                       int32_t* info, int batch, int nb);
+template <typename T>
+cds_status_t getrs_run(Ctx& c, int trans, int n, int nrhs, const T* LU, int64_t lda, int64_t strideA,
+                       const int32_t* ipiv, int64_t strideP, T* B, int64_t ldb, int64_t strideB, int batch,
+                       void* ws, size_t ws_bytes);
+template <typename T>
+cds_status_t potrf_run(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int nb);
+template <typename T>
+cds_status_t potrs_run(Ctx& c, int n, int nrhs, const T* L, int64_t lda, T* B, int64_t ldb, void* ws, size_t ws_bytes);
+
+// small utility kernels
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s);
+
+}  // namespace cds

@@ -1,0 +1,595 @@
+// Blocked right-looking LU with partial pivoting (Sec. 2 of the paper: A = LU,
+// L unit lower, partial pivoting; k rank-1 updates delayed into one rank-k
+// update).  Kernels:
+//   panel_kernel   factors the m x jb panel A[k:n, k:k+jb] in one persistent
+//                  launch of G workgroups (256 rows each).  Each column step is
+//                  one all-to-all exchange of (|pivot candidate|, row) through
+//                  flag+payload words: every workgroup finds its local arg-max
+//                  with wave shuffles, publishes it, reads everybody's, and
+//                  agrees on the global pivot (lowest row on ties).  The panel
+//                  is processed in leaves of W columns held in registers; after
+//                  each leaf the row interchanges, the small triangular solve
+//                  and the update of the rest of the panel are done in the same
+//                  launch from the published rows.
+//   laswp_kernel   applies the panel's interchanges to the other columns as
+//                  per-leaf gather/scatter lists (coalesced over the contiguous
+//                  top rows, one line per scattered pivot row).
+//   trsm_kernel    U12 = L11^{-1} A12 (unit lower), LDS-blocked.
+// The trailing update A22 -= L21 U12 is the MFMA GEMM (gemm.hip).
+#include "common.hpp"
+#include "kernels.hpp"
+#include "mixed.hpp"
+#include <algorithm>
+
+namespace cds {
+
+namespace {
+
+constexpr int PNT = 256;    // threads (= rows) per panel workgroup
+constexpr int PCH = 64;     // column chunk of the in-panel update
+
+template <typename T>
+struct PanelArgs {
+  T* A; int64_t lda; int64_t strideA;
+  int n, k, jb;
+  int32_t* ipiv; int64_t strideP;
+  int32_t* info;
+  uint64_t* slots; int64_t slot_stride;   // words per matrix
+  int2* pairs; int* pair_cnt; int64_t pairs_stride;  // per matrix: [leaf][3W] pairs, [leaf] counts
+  int cnt_stride;                                     // counts per matrix
+  int* err;
+  int G;
+};
+
+template <typename T, int W>
+struct SlotLayout {
+  static constexpr int LLW = LLWords<T>::n;
+  int G, jb;
+  __host__ __device__ int64_t hdr_words() const { return 4; }
+  __host__ __device__ int64_t cs_par() const { return (int64_t)G * 4 + (int64_t)G * W * LLW + W * LLW; }
+  __host__ __device__ int64_t sw_par() const { return (int64_t)3 * W * jb * LLW; }
+  __host__ __device__ int64_t total() const { return 2 * cs_par() + 2 * sw_par(); }
+  __host__ __device__ int64_t hdr(int par, int g) const { return par * cs_par() + (int64_t)g * 4; }
+  __host__ __device__ int64_t cand(int par, int g) const { return par * cs_par() + (int64_t)G * 4 + (int64_t)g * W * LLW; }
+  __host__ __device__ int64_t rowj(int par) const { return par * cs_par() + (int64_t)G * 4 + (int64_t)G * W * LLW; }
+  __host__ __device__ int64_t sw(int par, int e) const { return 2 * cs_par() + par * sw_par() + (int64_t)e * jb * LLW; }
+};
+
+// Column-step exchange, executed by wave 0 of every panel workgroup.
+template <typename T, int W>
+__device__ __noinline__ void colstep_exchange(uint64_t* slots, SlotLayout<T, W> L, int g, int wl, int j, int par,
+                                              uint32_t flag, const T* red_mag, const int* red_row,
+                                              T (*cand)[W], const T* jrow_l, T* prow, T* jrow, int* s_p, int* err) {
+  constexpr int LLW = LLWords<T>::n;
+  const int lane = lane_id();
+  // this workgroup's candidate
+  T mag = lane < 4 ? red_mag[lane] : (T)-1;
+  int row = lane < 4 ? red_row[lane] : 0x7fffffff;
+  int wv = lane;
+  {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      T om = shfl_xor(mag, m);
+      int orow = shfl_xor(row, m);
+      int owv = shfl_xor(wv, m);
+      bool take = (om > mag) || (om == mag && orow < row);
+      mag = take ? om : mag;
+      row = take ? orow : row;
+      wv = take ? owv : wv;
+    }
+  }
+  // publish header and candidate row
+  uint64_t* hdr = slots + L.hdr(par, g);
+  if (lane == 0) {
+    ll_store_val(hdr, mag, flag);
+    ll_store(hdr + LLW, (uint32_t)row, flag);
+  }
+  if (mag >= (T)0 && lane < wl) ll_store_val(slots + L.cand(par, g) + lane * LLW, cand[wv][lane], flag);
+  if (j / PNT == g && lane < wl) ll_store_val(slots + L.rowj(par) + lane * LLW, jrow_l[lane], flag);
+  // gather all headers
+  T bm = (T)-1;
+  int br = 0x7fffffff;
+  for (int i = lane; i < L.G; i += kWave) {
+    const uint64_t* h = slots + L.hdr(par, i);
+    T mi = ll_load_val<T>(h, flag, err);
+    int ri = (int)ll_load(h + LLW, flag, err);
+    bool take = (mi > bm) || (mi == bm && ri < br);
+    bm = take ? mi : bm;
+    br = take ? ri : br;
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    T om = shfl_xor(bm, m);
+    int orow = shfl_xor(br, m);
+    bool take = (om > bm) || (om == bm && orow < br);
+    bm = take ? om : bm;
+    br = take ? orow : br;
+  }
+  const int p = br;
+  const int gp = p / PNT;
+  if (lane < wl) {
+    prow[lane] = ll_load_val<T>(slots + L.cand(par, gp) + lane * LLW, flag, err);
+    if (p != j) jrow[lane] = ll_load_val<T>(slots + L.rowj(par) + lane * LLW, flag, err);
+  }
+  if (lane == 0) *s_p = p;
+}
+
+// Compose the leaf's sequential interchanges (c0+cc <-> piv[cc]) into a list of
+// (dst, src) moves.  Entries 0..wl-1 are the top positions c0..c0+wl-1 (src may
+// equal dst); later entries are the other moved positions.  Wave 0 only.
+template <int W>
+__device__ void compose_leaf(const int* s_piv, int c0, int wl, int* s_dst, int* s_src, int* s_ne) {
+  const int lane = lane_id();
+  int mypos = -1, mysrc = -1, cnt = 0;   // lane L holds table entry L (2W <= 64)
+  for (int cc = 0; cc < wl; ++cc) {
+    const int a = c0 + cc, bb = s_piv[cc];
+    if (a == bb) continue;
+    uint64_t ma = __ballot(lane < cnt && mypos == a);
+    uint64_t mb = __ballot(lane < cnt && mypos == bb);
+    int ia = ma ? (__ffsll((unsigned long long)ma) - 1) : -1;
+    int ib = mb ? (__ffsll((unsigned long long)mb) - 1) : -1;
+    int sa = ia >= 0 ? __shfl(mysrc, ia) : a;
+    int sb = ib >= 0 ? __shfl(mysrc, ib) : bb;
+    if (ia < 0) { ia = cnt++; if (lane == ia) mypos = a; }
+    if (ib < 0) { ib = cnt++; if (lane == ib) mypos = bb; }
+    if (lane == ia) mysrc = sb;
+    if (lane == ib) mysrc = sa;
+  }
+  // top entries (the loop is uniform: every lane takes part in each shuffle)
+  const int d = c0 + lane;
+  int s = d;
+  for (int e = 0; e < cnt; ++e) {
+    const int pe = __shfl(mypos, e);
+    const int se = __shfl(mysrc, e);
+    if (pe == d) s = se;
+  }
+  if (lane < wl) {
+    s_dst[lane] = d;
+    s_src[lane] = s;
+  }
+  bool other = lane < cnt && mypos >= c0 + wl;
+  uint64_t mo = __ballot(other);
+  if (other) {
+    int idx = wl + __popcll(mo & ((1ull << lane) - 1ull));
+    s_dst[idx] = mypos;
+    s_src[idx] = mysrc;
+  }
+  if (lane == 0) *s_ne = wl + __popcll(mo);
+}
+
+template <typename T, int W>
+__global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
+  constexpr int LLW = LLWords<T>::n;
+  const int g = blockIdx.x, b = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m = P.n - P.k, jb = P.jb;
+  const int64_t lda = P.lda;
+  T* __restrict__ A = P.A + (size_t)b * P.strideA + P.k + (size_t)P.k * lda;
+  int32_t* ipiv = P.ipiv + (size_t)b * P.strideP + P.k;
+  uint64_t* slots = P.slots + (size_t)b * P.slot_stride;
+  int2* pairs = P.pairs + (size_t)b * P.pairs_stride;
+  int* pair_cnt = P.pair_cnt + (size_t)b * P.cnt_stride;
+  SlotLayout<T, W> L{P.G, jb};
+  const int row = g * PNT + tid;
+  const bool own = row < m;
+
+  __shared__ T red_mag[4];
+  __shared__ int red_row[4];
+  __shared__ T cand[4][W];
+  __shared__ T jrow_l[W];
+  __shared__ T prow[W];
+  __shared__ T jrow[W];
+  __shared__ int s_p;
+  __shared__ T L11[W][W + 1];
+  __shared__ int s_piv[W];
+  __shared__ int s_dst[3 * W], s_src[3 * W];
+  __shared__ int s_ne;
+  __shared__ T Ubuf[W][PCH + 1];
+
+  T a[W];
+  int leafc = 0;
+  for (int c0 = 0; c0 < jb; c0 += W, ++leafc) {
+    const int wl = min(W, jb - c0);
+    const bool act = own && row >= c0;
+#pragma unroll
+    for (int cc = 0; cc < W; ++cc) a[cc] = (act && cc < wl) ? A[row + (size_t)(c0 + cc) * lda] : (T)0;
+
+#pragma unroll
+    for (int cc = 0; cc < W; ++cc) {
+      if (cc < wl) {
+        const int j = c0 + cc;
+        const int par = j & 1;
+        const uint32_t flag = (uint32_t)(P.k + j + 1);
+        const bool cand_ok = own && row >= j;
+        T mag = cand_ok ? fabs(a[cc]) : (T)-1;
+        int r = cand_ok ? row : 0x7fffffff;
+        wave_argmax(mag, r);
+        if (cand_ok && row == r) {
+#pragma unroll
+          for (int c2 = 0; c2 < W; ++c2) cand[wave][c2] = a[c2];
+        }
+        if (lane == 0) { red_mag[wave] = mag; red_row[wave] = r; }
+        if (own && row == j) {
+#pragma unroll
+          for (int c2 = 0; c2 < W; ++c2) jrow_l[c2] = a[c2];
+        }
+        __syncthreads();
+        if (wave == 0)
+          colstep_exchange<T, W>(slots, L, g, wl, j, par, flag, red_mag, red_row, cand, jrow_l, prow, jrow, &s_p, P.err);
+        __syncthreads();
+        const int p = s_p;
+        const T piv = prow[cc];
+        if (own && row == j) {
+#pragma unroll
+          for (int c2 = 0; c2 < W; ++c2) a[c2] = prow[c2];
+        } else if (own && row == p) {
+#pragma unroll
+          for (int c2 = 0; c2 < W; ++c2) a[c2] = jrow[c2];
+        }
+        if (own && row > j && piv != (T)0) {
+          const T l = a[cc] / piv;
+          a[cc] = l;
+#pragma unroll
+          for (int c2 = cc + 1; c2 < W; ++c2) a[c2] = (c2 < wl) ? (a[c2] - l * prow[c2]) : a[c2];
+        }
+        if (tid < W) L11[cc][tid] = prow[tid];
+        if (tid == 0) {
+          s_piv[cc] = p;
+          if (g == 0) {
+            ipiv[j] = P.k + p + 1;
+            if (piv == (T)0) atomicCAS(P.info + b, 0, P.k + j + 1);
+          }
+        }
+      }
+    }
+    // write back the leaf columns
+    if (act) {
+#pragma unroll
+      for (int cc = 0; cc < W; ++cc)
+        if (cc < wl) A[row + (size_t)(c0 + cc) * lda] = a[cc];
+    }
+    __syncthreads();
+    if (wave == 0) compose_leaf<W>(s_piv, c0, wl, s_dst, s_src, &s_ne);
+    __syncthreads();
+    const int ne = s_ne;
+    const int spar = leafc & 1;
+    const uint32_t sflag = (uint32_t)(P.k + c0 + 1);
+    const int nv = jb - wl;   // non-leaf columns of the panel
+    // record the moves for the trailing/left interchange kernel
+    if (g == 0) {
+      for (int e = tid; e < 3 * W; e += PNT) {
+        // entries with src == dst are recorded too (harmless), count covers all
+        if (e < ne) pairs[leafc * 3 * W + e] = make_int2(s_dst[e] + P.k, s_src[e] + P.k);
+      }
+      if (tid == 0) pair_cnt[leafc] = ne;
+    }
+    if (nv > 0) {
+      // publish rows this workgroup is the source of
+      for (int e = 0; e < ne; ++e) {
+        const int src = s_src[e];
+        if (src / PNT != g) continue;
+        uint64_t* sw = slots + L.sw(spar, e);
+        for (int idx = tid; idx < nv; idx += PNT) {
+          const int col = idx < c0 ? idx : idx + wl;
+          ll_store_val(sw + (int64_t)idx * LLW, A[src + (size_t)col * lda], sflag);
+        }
+      }
+      __syncthreads();
+      // move rows into the destinations this workgroup owns
+      for (int e = 0; e < ne; ++e) {
+        const int dst = s_dst[e], src = s_src[e];
+        if (dst / PNT != g || dst == src) continue;
+        const uint64_t* sw = slots + L.sw(spar, e);
+        for (int idx = tid; idx < nv; idx += PNT) {
+          const int col = idx < c0 ? idx : idx + wl;
+          A[dst + (size_t)col * lda] = ll_load_val<T>(sw + (int64_t)idx * LLW, sflag, P.err);
+        }
+      }
+      __syncthreads();
+      // U_right = L11^{-1} P_top and the update of the rows below, chunk by chunk
+      const int c1 = c0 + wl;
+      for (int x0 = c1; x0 < jb; x0 += PCH) {
+        const int cw = min(PCH, jb - x0);
+        for (int idx = tid; idx < wl * cw; idx += PNT) {
+          const int cc = idx / cw, x = idx % cw;
+          const int col = x0 + x;
+          Ubuf[cc][x] = ll_load_val<T>(slots + L.sw(spar, cc) + (int64_t)(col - wl) * LLW, sflag, P.err);
+        }
+        __syncthreads();
+        if (tid < cw) {
+          for (int i = 1; i < wl; ++i) {
+            T s = Ubuf[i][tid];
+            for (int t = 0; t < i; ++t) s -= L11[i][t] * Ubuf[t][tid];
+            Ubuf[i][tid] = s;
+          }
+        }
+        __syncthreads();
+        for (int idx = tid; idx < wl * cw; idx += PNT) {
+          const int cc = idx / cw, x = idx % cw;
+          const int r = c0 + cc;
+          if (r / PNT == g) A[r + (size_t)(x0 + x) * lda] = Ubuf[cc][x];
+        }
+        if (own && row >= c1) {
+          for (int x = 0; x < cw; ++x) {
+            T* pa = A + row + (size_t)(x0 + x) * lda;
+            T v = *pa;
+#pragma unroll
+            for (int cc = 0; cc < W; ++cc)
+              if (cc < wl) v -= a[cc] * Ubuf[cc][x];
+            *pa = v;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// Apply the panel's interchanges (per-leaf move lists) to column ranges
+// [c_lo1, c_hi1) and [c_lo2, c_hi2).  One wave per column at a time.
+template <typename T, int W>
+__global__ void __launch_bounds__(256) laswp_kernel(T* A0, int64_t lda, int64_t strideA, const int2* pairs0,
+                                                    const int* cnt0, int64_t pairs_stride, int cnt_stride,
+                                                    int nleaves, int c_lo1, int c_hi1, int c_lo2, int c_hi2) {
+  const int b = blockIdx.y;
+  T* A = A0 + (size_t)b * strideA;
+  const int2* pairs = pairs0 + (size_t)b * pairs_stride;
+  const int* cnt = cnt0 + (size_t)b * cnt_stride;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n1 = c_hi1 - c_lo1, n2 = c_hi2 - c_lo2, ncols = n1 + n2;
+  constexpr int MAXE = 3 * W;
+  constexpr int PER = (MAXE + 63) / 64;
+  for (int cidx = blockIdx.x * 4 + wave; cidx < ncols; cidx += gridDim.x * 4) {
+    const int col = cidx < n1 ? c_lo1 + cidx : c_lo2 + (cidx - n1);
+    T* colp = A + (size_t)col * lda;
+    for (int l = 0; l < nleaves; ++l) {
+      const int ne = cnt[l];
+      const int2* pl = pairs + l * MAXE;
+      T v[PER];
+      int dst[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = lane + 64 * q;
+        dst[q] = -1;
+        if (e < ne) {
+          int2 pr = pl[e];
+          if (pr.x != pr.y) { dst[q] = pr.x; v[q] = colp[pr.y]; }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q)
+        if (dst[q] >= 0) colp[dst[q]] = v[q];
+    }
+  }
+}
+
+// U12 = L11^{-1} A12: L11 = jb x jb unit lower at L (ld lda), A12 = jb x ncols at X (ld lda).
+// Each workgroup solves CW columns held in LDS, 16-row blocks.
+template <typename T>
+__global__ void __launch_bounds__(256) trsm_llnu_kernel(const T* L0, T* X0, int64_t lda, int64_t strideA, int jb,
+                                                        int ncols, int CW) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* X = reinterpret_cast<T*>(smem_raw);   // [jb][CW+1]
+  const int b = blockIdx.y;
+  const T* L = L0 + (size_t)b * strideA;
+  T* Xg = X0 + (size_t)b * strideA;
+  const int c0 = blockIdx.x * CW;
+  const int cw = min(CW, ncols - c0);
+  const int tid = threadIdx.x;
+  const int P = CW + 1;
+  for (int idx = tid; idx < jb * cw; idx += 256) {
+    const int c = idx / jb, r = idx % jb;
+    X[r * P + c] = Xg[r + (size_t)(c0 + c) * lda];
+  }
+  __syncthreads();
+  constexpr int RB = 16;
+  for (int r0 = 0; r0 < jb; r0 += RB) {
+    const int rb = min(RB, jb - r0);
+    // diagonal block: one thread per column
+    if (tid < cw) {
+      for (int i = 1; i < rb; ++i) {
+        T s = X[(r0 + i) * P + tid];
+        for (int t = 0; t < i; ++t) s -= L[(r0 + i) + (size_t)(r0 + t) * lda] * X[(r0 + t) * P + tid];
+        X[(r0 + i) * P + tid] = s;
+      }
+    }
+    __syncthreads();
+    // rows below
+    const int nbelow = jb - r0 - rb;
+    for (int idx = tid; idx < nbelow * cw; idx += 256) {
+      const int r = r0 + rb + idx % nbelow, c = idx / nbelow;
+      T s = X[r * P + c];
+      for (int t = 0; t < rb; ++t) s -= L[r + (size_t)(r0 + t) * lda] * X[(r0 + t) * P + c];
+      X[r * P + c] = s;
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < jb * cw; idx += 256) {
+    const int c = idx / jb, r = idx % jb;
+    Xg[r + (size_t)(c0 + c) * lda] = X[r * P + c];
+  }
+}
+
+constexpr int kLeaf = 32;
+
+int default_nb(int n) {
+  if (n <= 2048) return 128;
+  return 256;
+}
+
+}  // namespace
+
+size_t getrf_ws_bytes(int n, int nb, int leaf, int batch, size_t elem) {
+  (void)leaf;
+  int jb = std::min(nb, std::max(n, 1));
+  int G = (std::max(n, 1) + PNT - 1) / PNT;
+  int llw = elem == 8 ? 2 : 1;
+  int64_t cs = (int64_t)G * 4 + (int64_t)G * kLeaf * llw + kLeaf * llw;
+  int64_t sw = (int64_t)3 * kLeaf * jb * llw;
+  int64_t slot_words = 2 * cs + 2 * sw;
+  int nleaves = (jb + kLeaf - 1) / kLeaf;
+  size_t slots = (size_t)slot_words * 8 * batch;
+  size_t pairs = (size_t)2 * batch * nleaves * 3 * kLeaf * sizeof(int2);
+  size_t cnts = (size_t)2 * batch * nleaves * sizeof(int);
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  return kErrRegion + al(slots) + al(pairs) + al(cnts);
+}
+
+template <typename T>
+cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, int32_t* ipiv, int64_t strideP,
+                            int32_t* info, int batch, int nb, int mode, int* scale_exp) {
+  if (batch <= 0) return CDS_SUCCESS;
+  if (n == 0) {
+    if (launch_fill_i32(info, batch, 0, c.s0) != hipSuccess) return CDS_HIP_ERROR;
+    return CDS_SUCCESS;
+  }
+  if (nb <= 0) nb = default_nb(n);
+  nb = std::max(kLeaf, (nb / kLeaf) * kLeaf);
+  const int W = kLeaf;
+  const int G = (n + PNT - 1) / PNT;
+  const int jbmax = std::min(nb, n);
+  const int llw = LLWords<T>::n;
+  const int64_t cs = (int64_t)G * 4 + (int64_t)G * W * llw + W * llw;
+  const int64_t swp = (int64_t)3 * W * jbmax * llw;
+  const int64_t slot_words = 2 * cs + 2 * swp;
+  const int nleaves = (jbmax + W - 1) / W;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  size_t need = getrf_ws_bytes(n, nb, W, batch, sizeof(T));
+  if (c.ws == nullptr || c.ws_bytes < need) return CDS_WORKSPACE_TOO_SMALL;
+  char* base = (char*)c.ws + kErrRegion;
+  uint64_t* slots = (uint64_t*)base;
+  size_t slots_b = al((size_t)slot_words * 8 * batch);
+  int2* pairs = (int2*)(base + slots_b);
+  size_t pairs_b = al((size_t)2 * batch * nleaves * 3 * W * sizeof(int2));
+  int* cnts = (int*)(base + slots_b + pairs_b);
+  const int64_t pairs_stride = (int64_t)nleaves * 3 * W;   // per matrix per parity
+
+  hipStream_t s0 = c.s0, s1 = c.s1;
+  if (launch_fill_i32(info, batch, 0, s0) != hipSuccess) return CDS_HIP_ERROR;
+  if (launch_fill_zero(slots, (size_t)slot_words * 8 * batch, s0) != hipSuccess) return CDS_HIP_ERROR;
+
+  const bool la = c.lookahead && n > nb && batch == 1;
+  // s1 joins s0's work so far
+  if (la) {
+    if (hipEventRecord(c.ev[0], s0) != hipSuccess) return CDS_HIP_ERROR;
+    if (hipStreamWaitEvent(s1, c.ev[0], 0) != hipSuccess) return CDS_HIP_ERROR;
+  }
+
+  auto panel = [&](int k, int jb, int parity, hipStream_t s) -> hipError_t {
+    PanelArgs<T> P;
+    P.A = A; P.lda = lda; P.strideA = strideA;
+    P.n = n; P.k = k; P.jb = jb;
+    P.ipiv = ipiv; P.strideP = strideP; P.info = info;
+    P.slots = slots; P.slot_stride = slot_words;
+    P.pairs = pairs + (size_t)parity * batch * pairs_stride;
+    P.pair_cnt = cnts + (size_t)parity * batch * nleaves;
+    P.pairs_stride = pairs_stride;
+    P.cnt_stride = nleaves;
+    P.err = c.err;
+    P.G = (n - k + PNT - 1) / PNT;
+    hipLaunchKernelGGL((panel_kernel<T, kLeaf>), dim3(P.G, batch), dim3(PNT), 0, s, P);
+    return hipGetLastError();
+  };
+  // interchanges + trsm + gemm on columns [cb, ce) for the panel at k (width jb)
+  auto update = [&](int k, int jb, int parity, int cb, int ce, bool left, hipStream_t s) -> hipError_t {
+    const int nl = (jb + W - 1) / W;
+    const int2* pr = pairs + (size_t)parity * batch * pairs_stride;
+    const int* pc = cnts + (size_t)parity * batch * nleaves;
+    int lo1 = 0, hi1 = left ? k : 0;
+    int ncols = (hi1 - lo1) + (ce - cb);
+    if (ncols > 0) {
+      int blocks = std::min(4096, (ncols + 3) / 4);
+      // pair counts are laid out per matrix with stride nleaves; laswp reads [b*nleaves + l]
+      hipLaunchKernelGGL((laswp_kernel<T, kLeaf>), dim3(blocks, batch), dim3(256), 0, s, A, lda, strideA, pr, pc,
+                         pairs_stride, nleaves, nl, lo1, hi1, cb, ce);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    if (ce > cb) {
+      const int nc = ce - cb;
+      int CW = (int)std::max<int64_t>(8, std::min<int64_t>(64, 65536 / ((int64_t)(jb + 0) * sizeof(T))));
+      size_t sm = (size_t)jb * (CW + 1) * sizeof(T);
+      hipLaunchKernelGGL((trsm_llnu_kernel<T>), dim3((nc + CW - 1) / CW, batch), dim3(256), sm, s,
+                         (const T*)(A + k + (size_t)k * lda), A + k + (size_t)cb * lda, lda, strideA, jb, nc, CW);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      const int mrem = n - k - jb;
+      const int* sc = nullptr;
+      if (mrem > 0 && mode == 2 && scale_exp != nullptr) {
+        // power-of-two scale of this launch's U12 block (one slot per stream)
+        int* slot = scale_exp + (s == c.s0 ? 0 : batch);
+        if constexpr (std::is_same<T, float>::value) {
+          e = launch_maxabs_exp(A + k + (size_t)cb * lda, lda, strideA, jb, nc, slot, batch, s);
+          if (e != hipSuccess) return e;
+        }
+        sc = slot;
+      }
+      if (mrem > 0) {
+        GemmArgs<T> ga;
+        ga.m = mrem; ga.n = nc; ga.k = jb;
+        ga.A = A + (k + jb) + (size_t)k * lda; ga.lda = lda; ga.strideA = strideA;
+        ga.B = A + k + (size_t)cb * lda; ga.ldb = lda; ga.strideB = strideA;
+        ga.C = A + (k + jb) + (size_t)cb * lda; ga.ldc = lda; ga.strideC = strideA;
+        ga.alpha = (T)-1; ga.transB = 0; ga.lower = 0; ga.scale_exp = sc; ga.guard = nullptr;
+        e = launch_gemm<T>(ga, batch, mode, s);
+        if (e != hipSuccess) return e;
+      }
+    }
+    return hipSuccess;
+  };
+
+  int step = 0;
+  if (!la) {
+    for (int k = 0; k < n; k += nb, ++step) {
+      const int jb = std::min(nb, n - k);
+      const int par = step & 1;
+      if (panel(k, jb, par, s0) != hipSuccess) return CDS_HIP_ERROR;
+      if (update(k, jb, par, k + jb, n, true, s0) != hipSuccess) return CDS_HIP_ERROR;
+    }
+    return CDS_SUCCESS;
+  }
+  // look-ahead: s0 carries panels and the next panel's columns, s1 the rest.
+  hipEvent_t evP = c.ev[1], evR = c.ev[2];
+  if (panel(0, std::min(nb, n), 0, s0) != hipSuccess) return CDS_HIP_ERROR;
+  bool have_rest = false;
+  for (int k = 0; k < n; k += nb, ++step) {
+    const int jb = std::min(nb, n - k);
+    const int par = step & 1;
+    const int kn = k + jb;                       // next panel start
+    const int jbn = std::min(nb, n - kn);        // next panel width (<= 0 if none)
+    if (hipEventRecord(evP, s0) != hipSuccess) return CDS_HIP_ERROR;   // panel k done
+    // s1: rest of the trailing matrix and the left interchanges
+    if (hipStreamWaitEvent(s1, evP, 0) != hipSuccess) return CDS_HIP_ERROR;
+    if (jbn > 0) {
+      if (update(k, jb, par, kn + jbn, n, true, s1) != hipSuccess) return CDS_HIP_ERROR;
+    } else {
+      if (update(k, jb, par, n, n, true, s1) != hipSuccess) return CDS_HIP_ERROR;
+    }
+    // s0: next panel's columns (need the previous rest update to have reached them)
+    if (jbn > 0) {
+      if (have_rest && hipStreamWaitEvent(s0, evR, 0) != hipSuccess) return CDS_HIP_ERROR;
+      if (update(k, jb, par, kn, kn + jbn, false, s0) != hipSuccess) return CDS_HIP_ERROR;
+      if (panel(kn, jbn, par ^ 1, s0) != hipSuccess) return CDS_HIP_ERROR;
+    }
+    if (hipEventRecord(evR, s1) != hipSuccess) return CDS_HIP_ERROR;
+    have_rest = true;
+  }
+  // join
+  if (hipStreamWaitEvent(s0, evR, 0) != hipSuccess) return CDS_HIP_ERROR;
+  return CDS_SUCCESS;
+}
+
+template <typename T>
+cds_status_t getrf_run(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, int32_t* ipiv, int64_t strideP,
+                       int32_t* info, int batch, int nb) {
+  return getrf_run_mode<T>(c, n, A, lda, strideA, ipiv, strideP, info, batch, nb, 0, nullptr);
+}
+
+template cds_status_t getrf_run<double>(Ctx&, int, double*, int64_t, int64_t, int32_t*, int64_t, int32_t*, int, int);
+template cds_status_t getrf_run<float>(Ctx&, int, float*, int64_t, int64_t, int32_t*, int64_t, int32_t*, int, int);
+template cds_status_t getrf_run_mode<float>(Ctx&, int, float*, int64_t, int64_t, int32_t*, int64_t, int32_t*, int,
+                                            int, int, int*);
+template cds_status_t getrf_run_mode<double>(Ctx&, int, double*, int64_t, int64_t, int32_t*, int64_t, int32_t*, int,
+                                             int, int, int*);
+
+}  // namespace cds

@@ -1,0 +1,626 @@
+// Mixed-precision solve with FP64 iterative refinement (an extension of the
+// paper's direct method, Sec. 2: factor once, then triangular solves; here the
+// factorization runs in FP32 or with BF16/FP16 update operands and the FP64
+// accuracy is recovered by refinement with an FP64 residual).
+//
+//   convert_kernel   A64 -> A32 (RNE) and the row sums of |A| (for ||A||_inf).
+//   residual_kernel  R = B - A X in FP64, with ||R(:,c)||_inf and ||X(:,c)||_inf.
+//   control_kernel   backward error eta, stopping rule, per-matrix active flag
+//                    that turns every later kernel of the loop into a no-op.
+//   outer_kernel     C = alpha X Y^T (the adjoint's Abar = -bbar x^T).
+#include "common.hpp"
+#include "kernels.hpp"
+#include "solve.hpp"
+#include "mixed.hpp"
+#include <algorithm>
+#include <vector>
+
+namespace cds {
+
+namespace {
+
+// order-preserving atomic max for non-negative doubles (NaN sorts above +inf)
+__device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
+  unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+  atomicMax(reinterpret_cast<unsigned long long*>(p), bits);
+}
+
+// One workgroup per 64 rows; wave w streams the columns j = w, w+4, ...
+__global__ void __launch_bounds__(256) convert_kernel(const double* A0, int64_t lda, int64_t strideA, float* B0,
+                                                      int64_t ldb, int64_t strideB, int n, double* anorm) {
+  const int b = blockIdx.y;
+  const double* A = A0 + (size_t)b * strideA;
+  float* Bf = B0 + (size_t)b * strideB;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = blockIdx.x * 64 + lane;
+  __shared__ double part[4][64];
+  double s = 0.0;
+  if (r < n) {
+    for (int j = wave; j < n; j += 4) {
+      const double v = A[r + (size_t)j * lda];
+      Bf[r + (size_t)j * ldb] = (float)v;
+      s += fabs(v);
+    }
+  }
+  part[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0) {
+    double t = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+    t = wave_max(t);
+    if (lane == 0) atomic_max_nonneg(anorm + b, t);
+  }
+}
+
+// ||A||_inf only (when no conversion is needed)
+__global__ void __launch_bounds__(256) rownorm_kernel(const double* A0, int64_t lda, int64_t strideA, int n,
+                                                      double* anorm) {
+  const int b = blockIdx.y;
+  const double* A = A0 + (size_t)b * strideA;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = blockIdx.x * 64 + lane;
+  __shared__ double part[4][64];
+  double s = 0.0;
+  if (r < n)
+    for (int j = wave; j < n; j += 4) s += fabs(A[r + (size_t)j * lda]);
+  part[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0) {
+    double t = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+    t = wave_max(t);
+    if (lane == 0) atomic_max_nonneg(anorm + b, t);
+  }
+}
+
+// R = B - op(A) X (FP64).  op N: 64 rows per workgroup, waves split the columns.
+// op T: row i of A^T is column i of A: one wave per output, lanes split the sum.
+__global__ void __launch_bounds__(256) residual_kernel(const double* A0, int64_t lda, int64_t strideA,
+                                                       const double* X0, int64_t ldx, int64_t strideX,
+                                                       const double* B0, int64_t ldb, int64_t strideB, double* R0,
+                                                       int64_t ldr, int64_t strideR, int n, int nrhs, int trans,
+                                                       double* rnorm, double* xnorm, const int* active) {
+  const int b = blockIdx.y;
+  if (active && active[b] == 0) return;
+  const double* A = A0 + (size_t)b * strideA;
+  const double* X = X0 + (size_t)b * strideX;
+  const double* B = B0 + (size_t)b * strideB;
+  double* R = R0 + (size_t)b * strideR;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ double part[4][64];
+  for (int c = 0; c < nrhs; ++c) {
+    const double* x = X + (size_t)c * ldx;
+    if (!trans) {
+      const int r = blockIdx.x * 64 + lane;
+      double s = 0.0;
+      if (r < n)
+        for (int j = wave; j < n; j += 4) s = fma(A[r + (size_t)j * lda], x[j], s);
+      part[wave][lane] = s;
+      __syncthreads();
+      if (wave == 0) {
+        double rv = 0.0;
+        if (r < n) {
+          rv = B[r + (size_t)c * ldb] - ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]));
+          R[r + (size_t)c * ldr] = rv;
+        }
+        double m = wave_max(fabs(rv));
+        double xm = wave_max(r < n ? fabs(x[r]) : 0.0);
+        if (lane == 0) {
+          atomic_max_nonneg(rnorm + (size_t)b * nrhs + c, m);
+          atomic_max_nonneg(xnorm + (size_t)b * nrhs + c, xm);
+        }
+      }
+      __syncthreads();
+    } else {
+      // 64 outputs per workgroup, 16 per wave
+      double mloc = 0.0, xloc = 0.0;
+      for (int o = 0; o < 16; ++o) {
+        const int i = blockIdx.x * 64 + wave * 16 + o;
+        if (i >= n) break;
+        double s = 0.0;
+        const double* col = A + (size_t)i * lda;
+        for (int j = lane; j < n; j += 64) s = fma(col[j], x[j], s);
+        s = wave_sum(s);
+        const double rv = B[i + (size_t)c * ldb] - s;
+        if (lane == 0) R[i + (size_t)c * ldr] = rv;
+        mloc = fmax(mloc, fabs(rv));
+        xloc = fmax(xloc, fabs(x[i]));
+      }
+      if (lane == 0) {
+        atomic_max_nonneg(rnorm + (size_t)b * nrhs + c, mloc);
+        atomic_max_nonneg(xnorm + (size_t)b * nrhs + c, xloc);
+      }
+    }
+  }
+}
+
+// Refinement state per matrix: eta history and the active flag.
+struct IrState {
+  double eta_prev, eta_prev2;
+  int active;
+  int done;
+};
+
+// One thread per matrix.  it = number of corrections applied so far.
+__global__ void control_kernel(int batch, int nrhs, int it, int max_iter, double tol, double success_tol,
+                               const double* anorm, double* rnorm, double* xnorm, IrState* st,
+                               cds_ir_result_t* res, int* active, const int32_t* info) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  IrState& s = st[b];
+  if (it == 0) {
+    s.eta_prev = s.eta_prev2 = INFINITY;
+    s.done = 0;
+    res[b].info = info ? info[b] : 0;
+    res[b].fell_back = 0;
+    res[b].iters = 0;
+  }
+  if (s.done) { active[b] = 0; return; }
+  double eta = 0.0;
+  const double na = anorm[b];
+  for (int c = 0; c < nrhs; ++c) {
+    const double rn = rnorm[(size_t)b * nrhs + c], xn = xnorm[(size_t)b * nrhs + c];
+    double e;
+    if (rn == 0.0) e = 0.0;
+    else if (na * xn > 0.0) e = rn / (na * xn);
+    else e = INFINITY;
+    if (!(e <= eta)) eta = e;   // NaN propagates
+    rnorm[(size_t)b * nrhs + c] = 0.0;
+    xnorm[(size_t)b * nrhs + c] = 0.0;
+  }
+  if (it == 0) res[b].eta0 = eta;
+  res[b].eta = eta;
+  res[b].iters = it;
+  int reason = 0;
+  if (info && info[b] != 0) reason = 5;
+  else if (!(eta == eta) || eta == INFINITY) reason = 4;
+  else if (eta <= tol) reason = 1;
+  else if (it >= 2 && eta > 0.5 * s.eta_prev && s.eta_prev > 0.5 * s.eta_prev2) reason = 2;
+  else if (it >= max_iter) reason = 3;
+  s.eta_prev2 = s.eta_prev;
+  s.eta_prev = eta;
+  if (reason) {
+    s.done = 1;
+    active[b] = 0;
+    res[b].stop_reason = reason;
+    res[b].converged = (eta <= success_tol) ? 1 : 0;
+  } else {
+    active[b] = 1;
+    res[b].stop_reason = 0;
+    res[b].converged = 0;
+  }
+}
+
+__global__ void outer_kernel(int m, int n, int k, double alpha, const double* X0, int64_t ldx, int64_t strideX,
+                             const double* Y0, int64_t ldy, int64_t strideY, double* C0, int64_t ldc,
+                             int64_t strideC) {
+  const int b = blockIdx.z;
+  const double* X = X0 + (size_t)b * strideX;
+  const double* Y = Y0 + (size_t)b * strideY;
+  double* C = C0 + (size_t)b * strideC;
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j0 = blockIdx.y * 64;
+  if (i >= m) return;
+  for (int jj = threadIdx.x >> 6; jj < 64; jj += 4) {
+    const int j = j0 + jj;
+    if (j >= n) break;
+    double s = 0.0;
+    for (int t = 0; t < k; ++t) s = fma(X[i + (size_t)t * ldx], Y[j + (size_t)t * ldy], s);
+    C[i + (size_t)j * ldc] = alpha * s;
+  }
+}
+
+__global__ void set_active_kernel(int* active, int batch) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < batch) active[b] = 1;
+}
+
+__global__ void copy_d_kernel(const double* A0, int64_t lda, int64_t strideA, double* B0, int64_t ldb,
+                              int64_t strideB, int rows, int cols) {
+  const int b = blockIdx.y;
+  const double* A = A0 + (size_t)b * strideA;
+  double* Bd = B0 + (size_t)b * strideB;
+  const int64_t total = (int64_t)rows * cols;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % rows), j = (int)(idx / rows);
+    Bd[i + (size_t)j * ldb] = A[i + (size_t)j * lda];
+  }
+}
+
+// power-of-two scale for FP16 update operands: 2^e * max|B| lands near 2^14
+__global__ void maxabs_exp_kernel(const float* B0, int64_t ldb, int64_t strideB, int rows, int cols, int* out,
+                                  int clear_only) {
+  (void)clear_only;
+  const int b = blockIdx.y;
+  const float* B = B0 + (size_t)b * strideB;
+  __shared__ float part[4];
+  float m = 0.f;
+  const int64_t total = (int64_t)rows * cols;
+  for (int64_t idx = threadIdx.x; idx < total; idx += blockDim.x) {
+    const int i = (int)(idx % rows), j = (int)(idx / rows);
+    m = fmaxf(m, fabsf(B[i + (size_t)j * ldb]));
+  }
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]));
+    int e = 0;
+    if (t > 0.f && t == t && t < INFINITY) {
+      int ex;
+      frexpf(t, &ex);      // t in [2^(ex-1), 2^ex)
+      e = 14 - ex;
+      e = max(-100, min(100, e));
+    }
+    out[b] = e;
+  }
+}
+
+// max_j sum_i |A(i, j)| = ||A^T||_inf; one wave per column
+__global__ void __launch_bounds__(256) colnorm_kernel(const double* A0, int64_t lda, int64_t strideA, int n,
+                                                      double* anorm) {
+  const int b = blockIdx.y;
+  const double* A = A0 + (size_t)b * strideA;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int j = blockIdx.x * 4 + wave;
+  double s = 0.0;
+  if (j < n)
+    for (int i = lane; i < n; i += 64) s += fabs(A[i + (size_t)j * lda]);
+  s = wave_sum(s);
+  if (lane == 0 && j < n) atomic_max_nonneg(anorm + b, s);
+}
+
+// Symmetric matrix held in its lower triangle: row r of A is A(r, 0..r) followed by
+// A(r+1.., r) (column r below the diagonal).  Converts the lower triangle to FP32
+// (the strict upper triangle of the copy is not written) and computes ||A||_inf.
+__global__ void __launch_bounds__(256) convert_sym_kernel(const double* A, int64_t lda, float* Bf, int64_t ldb, int n,
+                                                          double* anorm) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = blockIdx.x * 64 + lane;
+  __shared__ double part[4][64];
+  __shared__ double colp[64];
+  double s = 0.0;
+  if (r < n) {
+    for (int j = wave; j <= r; j += 4) {
+      const double v = A[r + (size_t)j * lda];
+      Bf[r + (size_t)j * ldb] = (float)v;
+      s += fabs(v);
+    }
+  }
+  part[wave][lane] = s;
+  for (int o = 0; o < 16; ++o) {
+    const int loc = wave * 16 + o;
+    const int rr = blockIdx.x * 64 + loc;
+    double t = 0.0;
+    if (rr < n)
+      for (int i = rr + 1 + lane; i < n; i += 64) t += fabs(A[i + (size_t)rr * lda]);
+    t = wave_sum(t);
+    if (lane == 0) colp[loc] = t;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    double t = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane] + colp[lane];
+    t = wave_max(t);
+    if (lane == 0) atomic_max_nonneg(anorm, t);
+  }
+}
+
+// R = B - A X for symmetric A held in its lower triangle (same split as above).
+__global__ void __launch_bounds__(256) residual_sym_kernel(const double* A, int64_t lda, const double* X, int64_t ldx,
+                                                           const double* B, int64_t ldb, double* R, int64_t ldr,
+                                                           int n, int nrhs, double* rnorm, double* xnorm,
+                                                           const int* active) {
+  if (active && active[0] == 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = blockIdx.x * 64 + lane;
+  __shared__ double part[4][64];
+  __shared__ double colp[64];
+  for (int c = 0; c < nrhs; ++c) {
+    const double* x = X + (size_t)c * ldx;
+    double s = 0.0;
+    if (r < n)
+      for (int j = wave; j <= r; j += 4) s = fma(A[r + (size_t)j * lda], x[j], s);
+    part[wave][lane] = s;
+    for (int o = 0; o < 16; ++o) {
+      const int loc = wave * 16 + o;
+      const int rr = blockIdx.x * 64 + loc;
+      double t = 0.0;
+      if (rr < n)
+        for (int i = rr + 1 + lane; i < n; i += 64) t = fma(A[i + (size_t)rr * lda], x[i], t);
+      t = wave_sum(t);
+      if (lane == 0) colp[loc] = t;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      double rv = 0.0;
+      if (r < n) {
+        rv = B[r + (size_t)c * ldb] -
+             (((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) + colp[lane]);
+        R[r + (size_t)c * ldr] = rv;
+      }
+      double m = wave_max(fabs(rv));
+      double xm = wave_max(r < n ? fabs(x[r]) : 0.0);
+      if (lane == 0) {
+        atomic_max_nonneg(rnorm + c, m);
+        atomic_max_nonneg(xnorm + c, xm);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void fallback_result_kernel(int nrhs, const double* anorm, double* rnorm, double* xnorm,
+                                       cds_ir_result_t* res, const int32_t* info, double success_tol) {
+  double eta = 0.0;
+  for (int c = 0; c < nrhs; ++c) {
+    const double rn = rnorm[c], xn = xnorm[c];
+    double e = rn == 0.0 ? 0.0 : ((*anorm) * xn > 0.0 ? rn / ((*anorm) * xn) : INFINITY);
+    if (!(e <= eta)) eta = e;
+    rnorm[c] = 0.0;
+    xnorm[c] = 0.0;
+  }
+  res->eta = eta;
+  res->fell_back = 1;
+  res->info = *info;
+  res->converged = (*info == 0 && eta <= success_tol) ? 1 : 0;
+}
+
+}  // namespace
+
+hipError_t launch_maxabs_exp(const float* B, int64_t ldb, int64_t strideB, int rows, int cols, int* out, int batch,
+                             hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(maxabs_exp_kernel, dim3(1, batch), dim3(256), 0, s, B, ldb, strideB, rows, cols, out, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_outer(int m, int n, int k, double alpha, const double* X, int64_t ldx, int64_t strideX,
+                        const double* Y, int64_t ldy, int64_t strideY, double* C, int64_t ldc, int64_t strideC,
+                        int batch, hipStream_t s) {
+  if (m <= 0 || n <= 0 || batch <= 0) return hipSuccess;
+  dim3 grid((m + 63) / 64, (n + 63) / 64, batch);
+  hipLaunchKernelGGL(outer_kernel, grid, dim3(256), 0, s, m, n, k, alpha, X, ldx, strideX, Y, ldy, strideY, C, ldc,
+                     strideC);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// workspace of the refinement loop (after the error region):
+//   anorm, rnorm, xnorm, state, active, scale (2 per matrix), info, perm, gmap, R,
+//   [FP64 fallback copy and pivots], then the inner region for the factorization /
+//   solves (which keeps its own error region view at the same error word).
+// ---------------------------------------------------------------------------------
+static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static size_t ir_small_bytes(int n, int nrhs, int batch) {
+  return al256(batch * 8) + 2 * al256((size_t)batch * nrhs * 8) + al256(batch * sizeof(IrState)) +
+         al256(batch * 4) + al256(batch * 4 * 2) + al256(batch * 4) + 2 * al256((size_t)batch * n * 4) +
+         al256((size_t)batch * n * nrhs * 8);
+}
+
+size_t ir_ws_bytes(int n, int nrhs, int batch, int nb, int chol, int fallback) {
+  size_t inner = chol ? std::max(potrf_ws_bytes(n, nb, 4), getrs_ws_bytes(n, nrhs, batch, 4))
+                      : std::max(getrf_ws_bytes(n, nb, 32, batch, 4), getrs_ws_bytes(n, nrhs, batch, 4));
+  size_t fb = 0;
+  if (fallback) {
+    inner = std::max(inner, chol ? potrf_ws_bytes(n, nb, 8) : getrf_ws_bytes(n, nb, 32, batch, 8));
+    inner = std::max(inner, getrs_ws_bytes(n, nrhs, batch, 8));
+    fb = al256((size_t)batch * n * n * 8) + al256((size_t)batch * n * 4) + al256(batch * 4);
+  }
+  return kErrRegion + ir_small_bytes(n, nrhs, batch) + fb + inner;
+}
+
+struct IrWs {
+  double* anorm; double* rnorm; double* xnorm; IrState* st; int* active; int* scale; int32_t* info;
+  int32_t* perm; int32_t* gmap; double* R;
+  double* fbA; int32_t* fbpiv; int32_t* fbinfo;
+  void* inner; size_t inner_bytes;
+};
+
+static bool carve(void* ws, size_t ws_bytes, int n, int nrhs, int batch, int fallback, IrWs& w) {
+  w = IrWs{};
+  char* p = (char*)ws + kErrRegion;
+  w.anorm = (double*)p; p += al256(batch * 8);
+  w.rnorm = (double*)p; p += al256((size_t)batch * nrhs * 8);
+  w.xnorm = (double*)p; p += al256((size_t)batch * nrhs * 8);
+  w.st = (IrState*)p; p += al256(batch * sizeof(IrState));
+  w.active = (int*)p; p += al256(batch * 4);
+  w.scale = (int*)p; p += al256(batch * 4 * 2);
+  w.info = (int32_t*)p; p += al256(batch * 4);
+  w.perm = (int32_t*)p; p += al256((size_t)batch * n * 4);
+  w.gmap = (int32_t*)p; p += al256((size_t)batch * n * 4);
+  w.R = (double*)p; p += al256((size_t)batch * n * nrhs * 8);
+  if (fallback) {
+    w.fbA = (double*)p; p += al256((size_t)batch * n * n * 8);
+    w.fbpiv = (int32_t*)p; p += al256((size_t)batch * n * 4);
+    w.fbinfo = (int32_t*)p; p += al256(batch * 4);
+  }
+  // inner drivers address their regions from (base + kErrRegion); give them a base
+  // whose "error region" overlaps the end of ours, and point their error word at ours.
+  w.inner = (void*)(p - kErrRegion);
+  size_t used = (size_t)(p - (char*)ws);
+  if (ws_bytes < used) return false;
+  w.inner_bytes = ws_bytes - used + kErrRegion;
+  return true;
+}
+
+// The refinement loop on existing low-precision factors: x0 = solve_lo(b), then
+// r = b - op(A) x (FP64), eta, stop test, d = solve_lo(r), x += d (FP64).
+static cds_status_t refine(Ctx& c, const IrWs& w, int trans, int chol, int n, int nrhs, const double* A, int64_t lda,
+                           int64_t strideA, const float* LU, int64_t ldlu, int64_t strideLU, const int32_t* perm,
+                           int64_t strideQ, const double* B, int64_t ldb, int64_t strideB, double* X, int64_t ldx,
+                           int64_t strideX, const cds_ir_params_t& prm, cds_ir_result_t* res, const int32_t* info,
+                           int batch) {
+  hipStream_t s = c.s0;
+  const int rblocks = (n + 63) / 64;
+  GetrsCore<float, double> g{};
+  g.trans = trans; g.chol = chol; g.n = n; g.nrhs = nrhs; g.batch = batch;
+  g.M = LU; g.lda = ldlu; g.strideA = strideLU;
+  g.ipiv = nullptr; g.strideP = 0; g.perm = perm; g.strideQ = strideQ;
+  g.B = B; g.ldb = ldb; g.strideB = strideB;
+  g.X = X; g.ldx = ldx; g.strideX = strideX; g.accumulate = 0;
+  g.active = nullptr; g.ws = w.inner; g.ws_bytes = w.inner_bytes;
+  cds_status_t st = getrs_core<float, double>(c, g);
+  if (st != CDS_SUCCESS) return st;
+  if (launch_fill_zero(w.rnorm, (size_t)batch * nrhs * 8, s) != hipSuccess) return CDS_HIP_ERROR;
+  if (launch_fill_zero(w.xnorm, (size_t)batch * nrhs * 8, s) != hipSuccess) return CDS_HIP_ERROR;
+  hipLaunchKernelGGL(set_active_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, w.active, batch);
+  if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
+  const int max_iter = prm.max_iter;
+  std::vector<int> h_active;
+  for (int it = 0; it <= max_iter; ++it) {
+    if (!chol) {
+      hipLaunchKernelGGL(residual_kernel, dim3(rblocks, batch), dim3(256), 0, s, A, lda, strideA, (const double*)X,
+                         ldx, strideX, B, ldb, strideB, w.R, (int64_t)n, (int64_t)n * nrhs, n, nrhs, trans, w.rnorm,
+                         w.xnorm, (const int*)w.active);
+    } else {
+      hipLaunchKernelGGL(residual_sym_kernel, dim3(rblocks), dim3(256), 0, s, A, lda, (const double*)X, ldx, B, ldb,
+                         w.R, (int64_t)n, n, nrhs, w.rnorm, w.xnorm, (const int*)w.active);
+    }
+    if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
+    hipLaunchKernelGGL(control_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, batch, nrhs, it, max_iter, prm.tol,
+                       prm.success_tol, (const double*)w.anorm, w.rnorm, w.xnorm, w.st, res, w.active, info);
+    if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
+    if (it == max_iter) break;
+    if (prm.host_check) {
+      // read the active flags on the host (synchronises the stream) and leave early
+      h_active.resize(batch);
+      if (hipMemcpyAsync(h_active.data(), w.active, sizeof(int) * batch, hipMemcpyDeviceToHost, s) != hipSuccess)
+        return CDS_HIP_ERROR;
+      if (hipStreamSynchronize(s) != hipSuccess) return CDS_HIP_ERROR;
+      bool any = false;
+      for (int v : h_active) any = any || v;
+      if (!any) break;
+    }
+    GetrsCore<float, double> d = g;
+    d.B = w.R; d.ldb = n; d.strideB = (int64_t)n * nrhs;
+    d.accumulate = 1;
+    d.active = w.active;
+    st = getrs_core<float, double>(c, d);
+    if (st != CDS_SUCCESS) return st;
+  }
+  return CDS_SUCCESS;
+}
+
+// FP64 redo of the systems whose refinement did not converge (host decides).
+static cds_status_t fallback_fp64(Ctx& c, const IrWs& w, int chol, int trans, int n, int nrhs, const double* A,
+                                  int64_t lda, int64_t strideA, const double* B, int64_t ldb, int64_t strideB,
+                                  double* X, int64_t ldx, int64_t strideX, cds_ir_result_t* res, int batch, int nb,
+                                  double success_tol) {
+  hipStream_t s = c.s0;
+  std::vector<cds_ir_result_t> h(batch);
+  if (hipMemcpyAsync(h.data(), res, sizeof(cds_ir_result_t) * batch, hipMemcpyDeviceToHost, s) != hipSuccess)
+    return CDS_HIP_ERROR;
+  if (hipStreamSynchronize(s) != hipSuccess) return CDS_HIP_ERROR;
+  Ctx ci = c;
+  ci.ws = w.inner; ci.ws_bytes = w.inner_bytes;
+  for (int b = 0; b < batch; ++b) {
+    if (h[b].converged) continue;
+    double* Ab = w.fbA + (size_t)b * n * n;
+    hipLaunchKernelGGL(copy_d_kernel, dim3(std::min(4096, (n * n + 255) / 256), 1), dim3(256), 0, s,
+                       A + (size_t)b * strideA, lda, (int64_t)0, Ab, (int64_t)n, (int64_t)0, n, n);
+    if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
+    hipLaunchKernelGGL(copy_d_kernel, dim3(std::min(4096, (n * nrhs + 255) / 256), 1), dim3(256), 0, s,
+                       B + (size_t)b * strideB, ldb, (int64_t)0, X + (size_t)b * strideX, ldx, (int64_t)0, n, nrhs);
+    if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
+    cds_status_t st;
+    if (!chol) {
+      st = getrf_run<double>(ci, n, Ab, n, 0, w.fbpiv, 0, w.fbinfo, 1, nb);
+      if (st != CDS_SUCCESS) return st;
+      st = getrs_run<double>(ci, trans, n, nrhs, Ab, n, 0, w.fbpiv, 0, X + (size_t)b * strideX, ldx, 0, 1, ci.ws,
+                             ci.ws_bytes);
+    } else {
+      st = potrf_run<double>(ci, n, Ab, n, w.fbinfo, nb);
+      if (st != CDS_SUCCESS) return st;
+      st = potrs_run<double>(ci, n, nrhs, Ab, n, X + (size_t)b * strideX, ldx, ci.ws, ci.ws_bytes);
+    }
+    if (st != CDS_SUCCESS) return st;
+    // residual of the FP64 solution into the result struct
+    if (launch_fill_zero(w.rnorm, (size_t)nrhs * 8, s) != hipSuccess) return CDS_HIP_ERROR;
+    if (launch_fill_zero(w.xnorm, (size_t)nrhs * 8, s) != hipSuccess) return CDS_HIP_ERROR;
+    if (!chol) {
+      hipLaunchKernelGGL(residual_kernel, dim3((n + 63) / 64, 1), dim3(256), 0, s, A + (size_t)b * strideA, lda,
+                         (int64_t)0, (const double*)(X + (size_t)b * strideX), ldx, (int64_t)0,
+                         B + (size_t)b * strideB, ldb, (int64_t)0, w.R, (int64_t)n, (int64_t)0, n, nrhs, trans,
+                         w.rnorm, w.xnorm, (const int*)nullptr);
+    } else {
+      hipLaunchKernelGGL(residual_sym_kernel, dim3((n + 63) / 64), dim3(256), 0, s, A, lda, (const double*)X, ldx, B,
+                         ldb, w.R, (int64_t)n, n, nrhs, w.rnorm, w.xnorm, (const int*)nullptr);
+    }
+    if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
+    hipLaunchKernelGGL(fallback_result_kernel, dim3(1), dim3(1), 0, s, nrhs, w.anorm + b, w.rnorm, w.xnorm, res + b,
+                       (const int32_t*)w.fbinfo, success_tol);
+    if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
+  }
+  return CDS_SUCCESS;
+}
+
+cds_status_t gesv_mixed_run(Ctx& c, int prec, int n, int nrhs, const double* A, int64_t lda, int64_t strideA,
+                            const double* B, int64_t ldb, int64_t strideB, double* X, int64_t ldx, int64_t strideX,
+                            float* LU, int64_t strideLU, int32_t* ipiv, int64_t strideP, const cds_ir_params_t& prm,
+                            cds_ir_result_t* res, int batch, int nb) {
+  if (batch == 0 || n == 0 || nrhs == 0) return CDS_SUCCESS;
+  hipStream_t s = c.s0;
+  IrWs w;
+  if (!carve(c.ws, c.ws_bytes, n, nrhs, batch, prm.fallback, w)) return CDS_WORKSPACE_TOO_SMALL;
+  if (launch_fill_zero(w.anorm, batch * 8, s) != hipSuccess) return CDS_HIP_ERROR;
+  hipLaunchKernelGGL(convert_kernel, dim3((n + 63) / 64, batch), dim3(256), 0, s, A, lda, strideA, LU, (int64_t)n,
+                     strideLU, n, w.anorm);
+  if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
+  Ctx ci = c;
+  ci.ws = w.inner; ci.ws_bytes = w.inner_bytes;
+  cds_status_t st = getrf_run_mode<float>(ci, n, LU, n, strideLU, ipiv, strideP, w.info, batch, nb, prec, w.scale);
+  if (st != CDS_SUCCESS) return st;
+  if (launch_perm(ipiv, strideP, n, w.perm, n, w.gmap, batch, s) != hipSuccess) return CDS_HIP_ERROR;
+  st = refine(ci, w, 0, 0, n, nrhs, A, lda, strideA, LU, n, strideLU, w.perm, n, B, ldb, strideB, X, ldx, strideX,
+              prm, res, w.info, batch);
+  if (st != CDS_SUCCESS) return st;
+  if (prm.fallback) return fallback_fp64(c, w, 0, 0, n, nrhs, A, lda, strideA, B, ldb, strideB, X, ldx, strideX, res,
+                                         batch, nb, prm.success_tol);
+  return CDS_SUCCESS;
+}
+
+cds_status_t getrs_mixed_run(Ctx& c, int trans, int n, int nrhs, const double* A, int64_t lda, int64_t strideA,
+                             const float* LU, int64_t strideLU, const int32_t* ipiv, int64_t strideP, const double* B,
+                             int64_t ldb, int64_t strideB, double* X, int64_t ldx, int64_t strideX,
+                             const cds_ir_params_t& prm, cds_ir_result_t* res, int batch) {
+  if (batch == 0 || n == 0 || nrhs == 0) return CDS_SUCCESS;
+  hipStream_t s = c.s0;
+  IrWs w;
+  if (!carve(c.ws, c.ws_bytes, n, nrhs, batch, 0, w)) return CDS_WORKSPACE_TOO_SMALL;
+  if (launch_fill_zero(w.anorm, batch * 8, s) != hipSuccess) return CDS_HIP_ERROR;
+  // ||op(A)||_inf: for A^T that is the largest column sum of |A|
+  if (!trans) {
+    hipLaunchKernelGGL(rownorm_kernel, dim3((n + 63) / 64, batch), dim3(256), 0, s, A, lda, strideA, n, w.anorm);
+  } else {
+    hipLaunchKernelGGL(colnorm_kernel, dim3((n + 3) / 4, batch), dim3(256), 0, s, A, lda, strideA, n, w.anorm);
+  }
+  if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
+  if (launch_fill_i32(w.info, batch, 0, s) != hipSuccess) return CDS_HIP_ERROR;
+  if (launch_perm(ipiv, strideP, n, w.perm, n, w.gmap, batch, s) != hipSuccess) return CDS_HIP_ERROR;
+  Ctx ci = c;
+  ci.ws = w.inner; ci.ws_bytes = w.inner_bytes;
+  return refine(ci, w, trans, 0, n, nrhs, A, lda, strideA, LU, n, strideLU, w.perm, n, B, ldb, strideB, X, ldx,
+                strideX, prm, res, w.info, batch);
+}
+
+cds_status_t posv_mixed_run(Ctx& c, int prec, int n, int nrhs, const double* A, int64_t lda, const double* B,
+                            int64_t ldb, double* X, int64_t ldx, float* L, const cds_ir_params_t& prm,
+                            cds_ir_result_t* res, int nb) {
+  if (n == 0 || nrhs == 0) return CDS_SUCCESS;
+  hipStream_t s = c.s0;
+  IrWs w;
+  if (!carve(c.ws, c.ws_bytes, n, nrhs, 1, prm.fallback, w)) return CDS_WORKSPACE_TOO_SMALL;
+  if (launch_fill_zero(w.anorm, 8, s) != hipSuccess) return CDS_HIP_ERROR;
+  // lower triangle to FP32 and the norm of the symmetric matrix
+  hipLaunchKernelGGL(convert_sym_kernel, dim3((n + 63) / 64, 1), dim3(256), 0, s, A, lda, L, (int64_t)n, n, w.anorm);
+  if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
+  Ctx ci = c;
+  ci.ws = w.inner; ci.ws_bytes = w.inner_bytes;
+  cds_status_t st = potrf_run_mode<float>(ci, n, L, n, w.info, nb, prec, w.scale);
+  if (st != CDS_SUCCESS) return st;
+  st = refine(ci, w, 0, 1, n, nrhs, A, lda, 0, L, n, 0, nullptr, 0, B, ldb, 0, X, ldx, 0, prm, res, w.info, 1);
+  if (st != CDS_SUCCESS) return st;
+  if (prm.fallback) return fallback_fp64(c, w, 1, 0, n, nrhs, A, lda, 0, B, ldb, 0, X, ldx, 0, res, 1, nb, prm.success_tol);
+  return CDS_SUCCESS;
+}
+
+}  // namespace cds

@@ -1,0 +1,376 @@
+// Triangular solves of the direct method (Sec. 2, step 2: Ly = b, Ux = y, by
+// forward and back substitution), and the row interchanges of P b.
+//
+//   perm_kernel        ipiv (sequential interchanges) -> row order perm, in LDS.
+//   gather / scatter   Y = B[perm] (op N) or X[perm] = W (op T), with type
+//                      conversion so that the refinement loop can solve in FP32
+//                      for an FP64 residual and add the correction in FP64.
+//   trsv_kernel        persistent, flag-synchronised blocked substitution.
+//                      Workgroups take 64-row blocks in dependency order from a
+//                      ticket counter (so a block only waits on blocks whose
+//                      workgroups are already running).  A block accumulates
+//                      the products with every solved block as soon as that
+//                      block's solution appears, solves its 64 x 64 diagonal
+//                      block in one wave, and publishes its solution through
+//                      flag+payload words.  The factor is read once per RHS
+//                      group.
+#include "common.hpp"
+#include "kernels.hpp"
+#include "solve.hpp"
+#include <algorithm>
+
+namespace cds {
+
+namespace {
+
+constexpr int BS = 64;      // rows per block
+constexpr int TNT = 256;    // threads per workgroup
+
+// ipiv -> perm: perm[i] = original row found at position i after all
+// interchanges.  One workgroup per matrix; the map lives in LDS when it fits.
+__global__ void __launch_bounds__(1024) perm_kernel(const int32_t* ipiv0, int64_t strideP, int n, int32_t* perm0,
+                                                    int64_t strideQ, int32_t* gmap0, int use_lds) {
+  extern __shared__ int smap[];
+  const int b = blockIdx.x;
+  const int32_t* ipiv = ipiv0 + (size_t)b * strideP;
+  int32_t* perm = perm0 + (size_t)b * strideQ;
+  int* map = use_lds ? smap : (gmap0 + (size_t)b * n);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) map[i] = i;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    for (int c0 = 0; c0 < n; c0 += 64) {
+      const int pv = (c0 + lane < n) ? ipiv[c0 + lane] - 1 : c0 + lane;
+      const int cnt = min(64, n - c0);
+      for (int t = 0; t < cnt; ++t) {
+        const int p = __shfl(pv, t);
+        const int s = c0 + t;
+        if (p > s && p < n && lane == 0) {   // valid interchanges only (p >= s by construction)
+          int x = map[s];
+          int y = map[p];
+          map[s] = y;
+          map[p] = x;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) perm[i] = map[i];
+}
+
+// Y[i, c] = (T) B[src(i), c] with src = perm[i] (gather = 1) or identity; skipped when active[b] == 0
+template <typename S, typename T>
+__global__ void gather_kernel(const S* B0, int64_t ldb, int64_t strideB, T* Y0, int64_t ldy, int64_t strideY,
+                              const int32_t* perm0, int64_t strideQ, int n, int nrhs, const int* active) {
+  const int b = blockIdx.y;
+  if (active && active[b] == 0) return;
+  const S* B = B0 + (size_t)b * strideB;
+  T* Y = Y0 + (size_t)b * strideY;
+  const int32_t* perm = perm0 ? perm0 + (size_t)b * strideQ : nullptr;
+  const int64_t total = (int64_t)n * nrhs;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % n), c = (int)(idx / n);
+    const int src = perm ? perm[i] : i;
+    Y[i + (size_t)c * ldy] = (T)B[src + (size_t)c * ldb];
+  }
+}
+
+// X[dst(i), c] = W[i, c] (or += when accumulate), dst = perm[i] (scatter) or identity
+template <typename T, typename S>
+__global__ void scatter_kernel(const T* W0, int64_t ldw, int64_t strideW, S* X0, int64_t ldx, int64_t strideX,
+                               const int32_t* perm0, int64_t strideQ, int n, int nrhs, int accumulate,
+                               const int* active) {
+  const int b = blockIdx.y;
+  if (active && active[b] == 0) return;
+  const T* W = W0 + (size_t)b * strideW;
+  S* X = X0 + (size_t)b * strideX;
+  const int32_t* perm = perm0 ? perm0 + (size_t)b * strideQ : nullptr;
+  const int64_t total = (int64_t)n * nrhs;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % n), c = (int)(idx / n);
+    const int dst = perm ? perm[i] : i;
+    S* p = X + dst + (size_t)c * ldx;
+    const S v = (S)W[i + (size_t)c * ldw];
+    *p = accumulate ? (*p + v) : v;
+  }
+}
+
+template <typename T>
+struct TrsvArgs {
+  const T* M; int64_t lda; int64_t strideA;
+  int n, nrhs, nblk, groups;
+  int trans, upper, unit;
+  T* Y; int64_t ldy; int64_t strideY;
+  uint64_t* slots; int64_t slot_stride;   // words per (batch, group)
+  int* tickets;                            // one per (batch, group)
+  int* err;
+  const int* active;
+  uint32_t flag;
+};
+
+// M(i, j) of the operator being solved: the stored triangle, or its transpose.
+template <typename T>
+__device__ __forceinline__ T mel(const TrsvArgs<T>& a, const T* M, int i, int j) {
+  return a.trans ? M[j + (size_t)i * a.lda] : M[i + (size_t)j * a.lda];
+}
+
+template <typename T, int NR>
+__global__ void __launch_bounds__(TNT) trsv_kernel(TrsvArgs<T> a) {
+  constexpr int LLW = LLWords<T>::n;
+  const int b = blockIdx.z, grp = blockIdx.y;
+  if (a.active && a.active[b] == 0) return;
+  const T* M = a.M + (size_t)b * a.strideA;
+  T* Y = a.Y + (size_t)b * a.strideY;
+  uint64_t* slots = a.slots + ((size_t)b * a.groups + grp) * a.slot_stride;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c_lo = grp * NR, nr = min(NR, a.nrhs - c_lo);
+
+  __shared__ int s_ticket;
+  __shared__ T Ms[BS][BS + 1];
+  __shared__ T ys[BS][NR];
+  __shared__ T red[4][BS][NR];
+  if (tid == 0) s_ticket = atomicAdd(a.tickets + (size_t)b * a.groups + grp, 1);
+  __syncthreads();
+  const int lb = s_ticket;
+  if (lb >= a.nblk) return;
+  const int bk = a.upper ? (a.nblk - 1 - lb) : lb;
+  const int r0 = bk * BS, rb = min(BS, a.n - r0);
+
+  // thread (i = row in block, q = quarter of the columns of a dependency block)
+  const int i = tid & 63, q = tid >> 6;
+  T acc[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) acc[r] = (T)0;
+
+  // cooperative load of the 64 x 64 block of the operator (rows r0.., cols c0..) into registers:
+  // element e = tid + 256 * u, (ii, jj) chosen so that global reads are coalesced.
+  T mreg[16];
+  auto load_block = [&](int cb) {
+    const int c0 = cb * BS, cw = min(BS, a.n - c0);
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + TNT * u;
+      const int fast = e & 63, slow = e >> 6;
+      // non-trans: M[r0+fast, c0+slow] contiguous in fast; trans: M^T(r0+slow, c0+fast) = A[c0+fast + (r0+slow)*lda]
+      int ii, jj;
+      if (!a.trans) { ii = fast; jj = slow; } else { ii = slow; jj = fast; }
+      mreg[u] = (ii < rb && jj < cw) ? mel(a, M, r0 + ii, c0 + jj) : (T)0;
+    }
+  };
+  auto store_block = [&]() {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + TNT * u;
+      const int fast = e & 63, slow = e >> 6;
+      if (!a.trans) Ms[fast][slow] = mreg[u]; else Ms[slow][fast] = mreg[u];
+    }
+  };
+
+  const int ndep = lb;   // number of dependency blocks
+  auto dep_block = [&](int d) { return a.upper ? (a.nblk - 1 - d) : d; };
+  if (ndep > 0) load_block(dep_block(0));
+  for (int d = 0; d < ndep; ++d) {
+    const int cb = dep_block(d);
+    store_block();
+    if (d + 1 < ndep) load_block(dep_block(d + 1));
+    // solution of block cb
+    const int c0 = cb * BS, cw = min(BS, a.n - c0);
+    for (int idx = tid; idx < BS * NR; idx += TNT) {
+      const int cc = idx % BS, r = idx / BS;
+      T v = (T)0;
+      if (cc < cw && r < nr) v = ll_load_val<T>(slots + ((size_t)cb * BS * NR + (size_t)r * BS + cc) * LLW, a.flag, a.err);
+      ys[cc][r] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int cc = q * 16; cc < q * 16 + 16; ++cc) {
+      const T mv = Ms[i][cc];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[r] += mv * ys[cc][r];
+    }
+    __syncthreads();
+  }
+  // reduce the four quarters, form the right-hand side
+#pragma unroll
+  for (int r = 0; r < NR; ++r) red[q][i][r] = acc[r];
+  load_block(bk);
+  store_block();
+  __syncthreads();
+  // diagonal block: wave w solves the right-hand sides r = w, w + 4, ...
+  {
+    const T dii = (lane < rb) ? Ms[lane][lane] : (T)1;
+    for (int r = wave; r < nr; r += 4) {
+      T rhs = (lane < rb) ? Y[r0 + lane + (size_t)(c_lo + r) * a.ldy] : (T)0;
+      T val = rhs - (red[0][lane][r] + red[1][lane][r] + red[2][lane][r] + red[3][lane][r]);
+      if (!a.upper) {
+        for (int t = 0; t < rb; ++t) {
+          T xt = __shfl(val, t);
+          if (!a.unit) xt = xt / __shfl(dii, t);
+          if (lane == t) val = xt;
+          if (lane > t) val -= Ms[lane][t] * xt;
+        }
+      } else {
+        for (int t = rb - 1; t >= 0; --t) {
+          T xt = __shfl(val, t);
+          if (!a.unit) xt = xt / __shfl(dii, t);
+          if (lane == t) val = xt;
+          if (lane < t) val -= Ms[lane][t] * xt;
+        }
+      }
+      if (lane < rb) {
+        ll_store_val(slots + ((size_t)bk * BS * NR + (size_t)r * BS + lane) * LLW, val, a.flag);
+        Y[r0 + lane + (size_t)(c_lo + r) * a.ldy] = val;
+      }
+    }
+  }
+}
+
+template <typename T, int NR>
+hipError_t launch_trsv_nr(const TrsvArgs<T>& a, int batch, hipStream_t s) {
+  dim3 grid(a.nblk, a.groups, batch);
+  hipLaunchKernelGGL((trsv_kernel<T, NR>), grid, dim3(TNT), 0, s, a);
+  return hipGetLastError();
+}
+
+int pick_nr(int nrhs) { return nrhs <= 1 ? 1 : (nrhs <= 8 ? 8 : 32); }
+
+}  // namespace
+
+size_t trsv_slot_bytes(int n, int nrhs, int batch, size_t elem) {
+  const int nr = pick_nr(nrhs);
+  const int groups = (nrhs + nr - 1) / nr;
+  const int nblk = (n + BS - 1) / BS;
+  const int llw = elem == 8 ? 2 : 1;
+  return (size_t)batch * groups * nblk * BS * nr * llw * 8;
+}
+
+size_t getrs_ws_bytes(int n, int nrhs, int batch, size_t elem) {
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  size_t perm = al((size_t)batch * n * 4);
+  size_t gmap = al((size_t)batch * n * 4);
+  size_t temp = al((size_t)batch * n * std::max(nrhs, 1) * elem);
+  size_t slots = al(trsv_slot_bytes(n, nrhs, batch, elem));
+  size_t tick = al((size_t)batch * 64 * 4);
+  return kErrRegion + perm + gmap + temp + slots + tick;
+}
+
+hipError_t launch_perm(const int32_t* ipiv, int64_t strideP, int n, int32_t* perm, int64_t strideQ, int32_t* gmap,
+                       int batch, hipStream_t s) {
+  if (n <= 0 || batch <= 0) return hipSuccess;
+  const bool lds = (size_t)n * 4 <= 160 * 1024;
+  size_t sm = lds ? (size_t)n * 4 : 0;
+  hipLaunchKernelGGL(perm_kernel, dim3(batch), dim3(1024), sm, s, ipiv, strideP, n, perm, strideQ, gmap, lds ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <typename T, typename S>
+cds_status_t getrs_core(Ctx& c, const GetrsCore<T, S>& g) {
+  const int n = g.n, nrhs = g.nrhs, batch = g.batch;
+  if (n == 0 || nrhs == 0 || batch == 0) return CDS_SUCCESS;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  char* base = (char*)g.ws + kErrRegion;
+  int32_t* perm = (int32_t*)base;
+  base += al((size_t)batch * n * 4);
+  int32_t* gmap = (int32_t*)base;
+  base += al((size_t)batch * n * 4);
+  T* temp = (T*)base;
+  base += al((size_t)batch * n * nrhs * sizeof(T));
+  uint64_t* slots = (uint64_t*)base;
+  const size_t slot_b = trsv_slot_bytes(n, nrhs, batch, sizeof(T));
+  base += al(slot_b);
+  int* tickets = (int*)base;
+  base += al((size_t)batch * 64 * 4);
+  if ((size_t)(base - (char*)g.ws) > g.ws_bytes) return CDS_WORKSPACE_TOO_SMALL;
+  hipStream_t s = c.s0;
+
+  const int32_t* P = g.perm;
+  int64_t strideQ = g.strideQ;
+  if (g.ipiv && !P) {
+    if (launch_perm(g.ipiv, g.strideP, n, perm, n, gmap, batch, s) != hipSuccess) return CDS_HIP_ERROR;
+    P = perm;
+    strideQ = n;
+  }
+  const int64_t strideT = (int64_t)n * nrhs;
+  const int gblocks = (int)std::min<int64_t>(2048, ((int64_t)n * nrhs + 255) / 256);
+  // right-hand side into the working buffer (permuted for op N)
+  hipLaunchKernelGGL((gather_kernel<S, T>), dim3(gblocks, batch), dim3(256), 0, s, g.B, g.ldb, g.strideB, temp,
+                     (int64_t)n, strideT, g.trans ? (const int32_t*)nullptr : P, strideQ, n, nrhs, g.active);
+  if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
+
+  const int nr = pick_nr(nrhs);
+  const int groups = (nrhs + nr - 1) / nr;
+  const int nblk = (n + BS - 1) / BS;
+  const int64_t slot_stride = (int64_t)nblk * BS * nr * LLWords<T>::n;
+  for (int pass = 0; pass < 2; ++pass) {
+    TrsvArgs<T> a;
+    a.M = g.M; a.lda = g.lda; a.strideA = g.strideA;
+    a.n = n; a.nrhs = nrhs; a.nblk = nblk; a.groups = groups;
+    a.Y = temp; a.ldy = n; a.strideY = strideT;
+    a.slots = slots; a.slot_stride = slot_stride;
+    a.tickets = tickets;
+    a.err = c.err;
+    a.active = g.active;
+    a.flag = (uint32_t)(pass + 1);
+    if (!g.chol) {
+      if (!g.trans) {           // L y = Pb (unit), U x = y
+        a.trans = 0; a.upper = pass; a.unit = pass == 0;
+      } else {                  // U^T z = b, L^T w = z (unit)
+        a.trans = 1; a.upper = pass; a.unit = pass == 1;
+      }
+    } else {                    // L y = b, L^T x = y
+      a.trans = pass; a.upper = pass; a.unit = 0;
+    }
+    // clear flags and tickets (fill kernels, no memset nodes)
+    if (launch_fill_zero(slots, slot_b, s) != hipSuccess) return CDS_HIP_ERROR;
+    if (launch_fill_i32(tickets, (int64_t)batch * groups, 0, s) != hipSuccess) return CDS_HIP_ERROR;
+    hipError_t e;
+    if (nr == 1) e = launch_trsv_nr<T, 1>(a, batch, s);
+    else if (nr == 8) e = launch_trsv_nr<T, 8>(a, batch, s);
+    else e = launch_trsv_nr<T, 32>(a, batch, s);
+    if (e != hipSuccess) return CDS_HIP_ERROR;
+  }
+  hipLaunchKernelGGL((scatter_kernel<T, S>), dim3(gblocks, batch), dim3(256), 0, s, temp, (int64_t)n, strideT, g.X,
+                     g.ldx, g.strideX, g.trans ? P : (const int32_t*)nullptr, strideQ, n, nrhs, g.accumulate,
+                     g.active);
+  if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
+  return CDS_SUCCESS;
+}
+
+template cds_status_t getrs_core<double, double>(Ctx&, const GetrsCore<double, double>&);
+template cds_status_t getrs_core<float, float>(Ctx&, const GetrsCore<float, float>&);
+template cds_status_t getrs_core<float, double>(Ctx&, const GetrsCore<float, double>&);
+
+template <typename T>
+cds_status_t getrs_run(Ctx& c, int trans, int n, int nrhs, const T* LU, int64_t lda, int64_t strideA,
+                       const int32_t* ipiv, int64_t strideP, T* B, int64_t ldb, int64_t strideB, int batch,
+                       void* ws, size_t ws_bytes) {
+  GetrsCore<T, T> g{};
+  g.trans = trans; g.chol = 0; g.n = n; g.nrhs = nrhs; g.batch = batch;
+  g.M = LU; g.lda = lda; g.strideA = strideA;
+  g.ipiv = ipiv; g.strideP = strideP; g.perm = nullptr; g.strideQ = 0;
+  g.B = B; g.ldb = ldb; g.strideB = strideB;
+  g.X = B; g.ldx = ldb; g.strideX = strideB; g.accumulate = 0;
+  g.active = nullptr; g.ws = ws; g.ws_bytes = ws_bytes;
+  return getrs_core<T, T>(c, g);
+}
+template cds_status_t getrs_run<double>(Ctx&, int, int, int, const double*, int64_t, int64_t, const int32_t*,
+                                        int64_t, double*, int64_t, int64_t, int, void*, size_t);
+template cds_status_t getrs_run<float>(Ctx&, int, int, int, const float*, int64_t, int64_t, const int32_t*,
+                                       int64_t, float*, int64_t, int64_t, int, void*, size_t);
+
+template <typename T>
+cds_status_t potrs_run(Ctx& c, int n, int nrhs, const T* L, int64_t lda, T* B, int64_t ldb, void* ws,
+                       size_t ws_bytes) {
+  GetrsCore<T, T> g{};
+  g.trans = 0; g.chol = 1; g.n = n; g.nrhs = nrhs; g.batch = 1;
+  g.M = L; g.lda = lda; g.strideA = 0;
+  g.ipiv = nullptr; g.perm = nullptr;
+  g.B = B; g.ldb = ldb; g.strideB = 0;
+  g.X = B; g.ldx = ldb; g.strideX = 0; g.accumulate = 0;
+  g.active = nullptr; g.ws = ws; g.ws_bytes = ws_bytes;
+  return getrs_core<T, T>(c, g);
+}
+template cds_status_t potrs_run<double>(Ctx&, int, int, const double*, int64_t, double*, int64_t, void*, size_t);
+template cds_status_t potrs_run<float>(Ctx&, int, int, const float*, int64_t, float*, int64_t, void*, size_t);
+
+}  // namespace cds

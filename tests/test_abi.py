@@ -1,0 +1,74 @@
+"""CPU checks of the C-ABI library: it loads, exports every function declared in
+include/cds.h, and rejects bad handles without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cds.h")
+LIB = os.path.join(ROOT, "paper_1511_07174_amd", "libcds.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(?:cds_status_t|const char\s*\*)\s+(cds_\w+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1511_07174_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ["cds_dgetrf", "cds_dgetrs", "cds_dpotrf", "cds_dpotrs", "cds_dgesv_mixed",
+                     "cds_dposv_mixed_vbatched", "cds_create", "cds_set_workspace"]:
+        assert required in names
+    assert len(names) >= 30
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    import paper_1511_07174_amd.cds as b
+    assert sorted(set(b.EXPORTED)) == declared_functions()
+
+
+def test_null_handle_is_rejected_before_any_work(lib):
+    lib.cds_dgetrf.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                               ctypes.c_void_p]
+    lib.cds_dgetrf.restype = ctypes.c_int
+    assert lib.cds_dgetrf(None, 4, None, 4, None, None) == 2     # CDS_NOT_INITIALIZED
+    lib.cds_status_string.restype = ctypes.c_char_p
+    lib.cds_status_string.argtypes = [ctypes.c_int]
+    assert lib.cds_status_string(1) == b"CDS_INVALID_VALUE"
+    assert lib.cds_status_string(99) == b"CDS_UNKNOWN_STATUS"
+
+
+def test_create_without_gpu_reports_an_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    lib.cds_create.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+    lib.cds_create.restype = ctypes.c_int
+    assert lib.cds_create(ctypes.byref(h)) in (3, 4)   # CDS_HIP_ERROR or CDS_ARCH_MISMATCH
+    assert not h.value
+
+
+def test_product_path_refuses_to_run_without_the_library(tmp_path, monkeypatch):
+    import paper_1511_07174_amd.cds as b
+    monkeypatch.setattr(b, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(b, "_lib", None)
+    with pytest.raises(b.CdsError):
+        b.lib()
