@@ -65,8 +65,21 @@ typedef enum {
   CDS_OPT_NB = 0,           /* block size override for getrf/potrf (0 = tuning table / default) */
   CDS_OPT_LOOKAHEAD = 1,    /* 1 (default): overlap the next panel with the trailing update */
   CDS_OPT_LEAF = 2,         /* panel leaf width (0 = default) */
-  CDS_OPT_PANEL_WGS = 3     /* max workgroups of the panel kernel (0 = default) */
+  CDS_OPT_PANEL_WGS = 3,    /* max workgroups of the panel kernel (0 = default) */
+  CDS_OPT_KERNEL_TIMING = 4 /* 1: record a pair of events around every launch of the kernel classes
+                               below, on the stream the kernel runs on (see cds_kernel_timing) */
 } cds_option_t;
+
+/* Kernel classes for cds_kernel_timing. */
+typedef enum {
+  CDS_KC_UPDATE = 0,     /* trailing-matrix update (MFMA GEMM / SYRK) */
+  CDS_KC_PANEL = 1,      /* panel factorization (LU) or diagonal block (Cholesky) */
+  CDS_KC_LASWP = 2,      /* row interchanges outside the panel */
+  CDS_KC_TRSM = 3,       /* U12 / L21 triangular solves of the factorization */
+  CDS_KC_TRSV = 4,       /* triangular solves of getrs / potrs */
+  CDS_KC_RESIDUAL = 5,   /* FP64 residual of the refinement */
+  CDS_KC_COUNT = 6
+} cds_kernel_class_t;
 
 /* Keys of the tuning table (cds_tune_set). */
 typedef enum {
@@ -95,6 +108,14 @@ cds_status_t cds_tune_clear(cds_handle_t handle);
  * word of the workspace: *h_err = 0 when every bounded wait completed. */
 cds_status_t cds_device_error(cds_handle_t handle, int32_t* h_err);
 const char* cds_status_string(cds_status_t status);
+/* Timing of the launches recorded since the last reset (CDS_OPT_KERNEL_TIMING = 1):
+ * synchronises, then returns the number of launches of class kc, their summed
+ * duration in ms (from the events around each launch) and their summed
+ * algorithmic flops and bytes (the operation's own count: 2mnk for an update,
+ * bytes read and written once for the bandwidth-bound kernels).  Host outputs. */
+cds_status_t cds_kernel_timing(cds_handle_t handle, int32_t kc, int64_t* h_launches, double* h_ms, double* h_flops,
+                               double* h_bytes);
+cds_status_t cds_kernel_timing_reset(cds_handle_t handle);
 
 typedef struct cds_ir_params_s cds_ir_params_t;
 

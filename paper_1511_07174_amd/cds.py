@@ -24,7 +24,8 @@ OP_N, OP_T = 0, 1
 LOWER = 0
 R_64F, R_32F = 0, 1
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
-OPT_NB, OPT_LOOKAHEAD, OPT_LEAF, OPT_PANEL_WGS = 0, 1, 2, 3
+OPT_NB, OPT_LOOKAHEAD, OPT_LEAF, OPT_PANEL_WGS, OPT_KERNEL_TIMING = 0, 1, 2, 3, 4
+KC = {"update": 0, "panel": 1, "laswp": 2, "trsm": 3, "trsv": 4, "residual": 5}
 TUNE_GETRF_NB, TUNE_POTRF_NB, TUNE_VBATCH_TILE = 0, 1, 2
 
 
@@ -93,6 +94,8 @@ def _declare(L):
         "cds_dposv_mixed": [P, ctypes.c_int, ctypes.c_int, I64, I64, P, I64, P, I64, P, I64, P, P, P],
         "cds_dposv_mixed_vbatched": [P, ctypes.c_int, I64, I64, P, P, P, P, P, P, P, I64, P, P, P, P, P],
         "cds_douter_strided_batched": [P, I64, I64, I64, D, P, I64, I64, P, I64, I64, P, I64, I64, I64],
+        "cds_kernel_timing": [P, I32, ctypes.POINTER(I64), ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)],
+        "cds_kernel_timing_reset": [P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -112,6 +115,7 @@ EXPORTED = [
     "cds_dpotrf", "cds_spotrf", "cds_dpotrs", "cds_spotrs",
     "cds_dgesv_mixed", "cds_dgesv_mixed_strided_batched", "cds_dgetrs_mixed_strided_batched",
     "cds_dposv_mixed", "cds_dposv_mixed_vbatched", "cds_douter_strided_batched",
+    "cds_kernel_timing", "cds_kernel_timing_reset",
 ]
 
 
@@ -211,6 +215,17 @@ class Handle:
 
     def tune_clear(self):
         check(lib().cds_tune_clear(self.h), "cds_tune_clear")
+
+    def kernel_timing(self, kc: str):
+        """(launches, ms, flops, bytes) summed over the recorded launches of a kernel class."""
+        n = ctypes.c_int64(0)
+        ms, fl, by = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0)
+        check(lib().cds_kernel_timing(self.h, KC[kc], ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl),
+                                      ctypes.byref(by)), "cds_kernel_timing")
+        return n.value, ms.value, fl.value, by.value
+
+    def kernel_timing_reset(self):
+        check(lib().cds_kernel_timing_reset(self.h), "cds_kernel_timing_reset")
 
     def device_error(self) -> int:
         v = ctypes.c_int32(0)

@@ -25,8 +25,9 @@ struct cds_handle_s {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  int nb_override = 0, lookahead = 1, leaf = 0, panel_wgs = 0;
+  int nb_override = 0, lookahead = 1, leaf = 0, panel_wgs = 0, timing = 0;
   std::vector<TuneEntry> tune;
+  cds::KTimer timer;
 };
 
 namespace {
@@ -53,7 +54,7 @@ int potrf_nb(const cds_handle_s* h, int dtype, int64_t n) {
 // getrf needs the resolved nb for its workspace size
 int resolved_nb(int nb, int64_t n) {
   if (nb <= 0) nb = n <= 2048 ? 128 : 256;
-  return std::max(32, (nb / 32) * 32);
+  return std::min(512, std::max(32, (nb / 32) * 32));
 }
 
 Ctx make_ctx(cds_handle_s* h) {
@@ -68,6 +69,7 @@ Ctx make_ctx(cds_handle_s* h) {
   c.lookahead = h->lookahead;
   c.leaf = h->leaf;
   c.panel_wgs = h->panel_wgs;
+  c.timer = h->timing ? &h->timer : nullptr;
   return c;
 }
 
@@ -241,7 +243,7 @@ cds_status_t cds_set_option(cds_handle_t h, cds_option_t opt, int64_t v) {
   if (!h) return CDS_NOT_INITIALIZED;
   switch (opt) {
     case CDS_OPT_NB:
-      if (v < 0 || v > 1024) return CDS_INVALID_VALUE;
+      if (v < 0 || v > 512) return CDS_INVALID_VALUE;
       h->nb_override = (int)v;
       return CDS_SUCCESS;
     case CDS_OPT_LOOKAHEAD:
@@ -256,6 +258,10 @@ cds_status_t cds_set_option(cds_handle_t h, cds_option_t opt, int64_t v) {
       if (v < 0) return CDS_INVALID_VALUE;
       h->panel_wgs = (int)v;
       return CDS_SUCCESS;
+    case CDS_OPT_KERNEL_TIMING:
+      if (v != 0 && v != 1) return CDS_INVALID_VALUE;
+      h->timing = (int)v;
+      return CDS_SUCCESS;
   }
   return CDS_INVALID_VALUE;
 }
@@ -264,7 +270,7 @@ cds_status_t cds_tune_set(cds_handle_t h, cds_tune_key_t key, cds_dtype_t dtype,
   if (!h) return CDS_NOT_INITIALIZED;
   if (key < CDS_TUNE_GETRF_NB || key > CDS_TUNE_VBATCH_TILE) return CDS_INVALID_VALUE;
   if (dtype != CDS_R_64F && dtype != CDS_R_32F) return CDS_INVALID_VALUE;
-  if (n_max < 0 || value <= 0 || value > 1024) return CDS_INVALID_VALUE;
+  if (n_max < 0 || value <= 0 || value > 512) return CDS_INVALID_VALUE;
   if (key == CDS_TUNE_VBATCH_TILE && value != 16 && value != 32) return CDS_INVALID_VALUE;
   for (auto& e : h->tune)
     if (e.key == key && e.dtype == dtype && e.n_max == n_max) { e.value = value; return CDS_SUCCESS; }
@@ -291,6 +297,38 @@ cds_status_t cds_device_error(cds_handle_t h, int32_t* h_err) {
     if (cds::launch_fill_zero(h->ws, cds::kErrRegion, h->stream) != hipSuccess) return CDS_HIP_ERROR;
     if (hipStreamSynchronize(h->stream) != hipSuccess) return CDS_HIP_ERROR;
   }
+  return CDS_SUCCESS;
+}
+
+cds_status_t cds_kernel_timing(cds_handle_t h, int32_t kc, int64_t* launches, double* ms, double* flops,
+                               double* bytes) {
+  if (!h) return CDS_NOT_INITIALIZED;
+  if (kc < 0 || kc >= CDS_KC_COUNT || !launches || !ms || !flops || !bytes) return CDS_INVALID_VALUE;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return CDS_HIP_ERROR;
+  if (hipStreamSynchronize(h->s1) != hipSuccess) return CDS_HIP_ERROR;
+  int64_t cnt = 0;
+  double t = 0.0, f = 0.0, b = 0.0;
+  for (const auto& r : h->timer.recs) {
+    if (r.kc != kc) continue;
+    float e = 0.f;
+    if (hipEventElapsedTime(&e, r.a, r.b) != hipSuccess) return CDS_HIP_ERROR;
+    ++cnt;
+    t += e;
+    f += r.flops;
+    b += r.bytes;
+  }
+  *launches = cnt;
+  *ms = t;
+  *flops = f;
+  *bytes = b;
+  return CDS_SUCCESS;
+}
+
+cds_status_t cds_kernel_timing_reset(cds_handle_t h) {
+  if (!h) return CDS_NOT_INITIALIZED;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return CDS_HIP_ERROR;
+  if (hipStreamSynchronize(h->s1) != hipSuccess) return CDS_HIP_ERROR;
+  h->timer.reset();
   return CDS_SUCCESS;
 }
 

@@ -162,18 +162,24 @@ cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int
   if (launch_fill_i32(info, 1, 0, s) != hipSuccess) return CDS_HIP_ERROR;
   if (n == 0) return CDS_SUCCESS;
   if (nb <= 0) nb = n <= 2048 ? 128 : 256;
-  nb = std::max(SB, (nb / SB) * SB);
+  nb = std::min(512, std::max(SB, (nb / SB) * SB));
   for (int k = 0; k < n; k += nb) {
     const int jb = std::min(nb, n - k);
     size_t psm = sizeof(T) * (size_t)(SB + 1) * (SB + jb);
-    hipLaunchKernelGGL((potf2_kernel<T>), dim3(1), dim3(256), psm, s, A, lda, k, jb, info);
+    {
+      KScope ks(c.timer, CDS_KC_PANEL, s, (double)jb * jb * jb / 3.0, (double)jb * jb * sizeof(T));
+      hipLaunchKernelGGL((potf2_kernel<T>), dim3(1), dim3(256), psm, s, A, lda, k, jb, info);
+    }
     if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
     const int rem = n - k - jb;
     if (rem <= 0) break;
     int RW = (int)std::max<int64_t>(8, std::min<int64_t>(64, 65536 / ((int64_t)(jb + 1) * sizeof(T))));
     size_t sm = (size_t)RW * (jb + 1) * sizeof(T);
-    hipLaunchKernelGGL((trsm_rlt_kernel<T>), dim3((rem + RW - 1) / RW), dim3(256), sm, s, A, lda, k, jb, rem, RW,
-                       (const int32_t*)info);
+    {
+      KScope ks(c.timer, CDS_KC_TRSM, s, (double)jb * jb * rem, 0.0);
+      hipLaunchKernelGGL((trsm_rlt_kernel<T>), dim3((rem + RW - 1) / RW), dim3(256), sm, s, A, lda, k, jb, rem, RW,
+                         (const int32_t*)info);
+    }
     if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
     GemmArgs<T> g;
     g.m = rem; g.n = rem; g.k = jb;
@@ -189,6 +195,7 @@ cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int
       }
       g.scale_exp = scale_exp;
     }
+    KScope ks(c.timer, CDS_KC_UPDATE, s, (double)rem * (rem + 1) * jb, (double)sizeof(T) * ((double)rem * (rem + 1) + (double)rem * jb));
     if (launch_gemm<T>(g, 1, mode, s) != hipSuccess) return CDS_HIP_ERROR;
   }
   return CDS_SUCCESS;

@@ -61,10 +61,23 @@ __device__ __forceinline__ void ll_store_f64(uint64_t* p, double v, uint32_t fla
   ll_store(p, (uint32_t)bits, flag);
   ll_store(p + 1, (uint32_t)(bits >> 32), flag);
 }
+// Both words are requested together (one round trip when the message is there).
 __device__ __forceinline__ double ll_load_f64(const uint64_t* p, uint32_t flag, int* err) {
-  uint64_t lo = ll_load(p, flag, err);
-  uint64_t hi = ll_load(p + 1, flag, err);
-  return __longlong_as_double((long long)((hi << 32) | lo));
+  long long spins = 0;
+  while (true) {
+    uint64_t w0 = __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t w1 = __hip_atomic_load(const_cast<uint64_t*>(p + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((uint32_t)(w0 >> 32) == flag && (uint32_t)(w1 >> 32) == flag)
+      return __longlong_as_double((long long)(((w1 & 0xffffffffull) << 32) | (w0 & 0xffffffffull)));
+    ++spins;
+    if ((spins & 4095) == 0) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return 0.0;
+      if (spins > kSpinLimit) {
+        atomicExch(err, (int)kErrSpinTimeout);
+        return 0.0;
+      }
+    }
+  }
 }
 __device__ __forceinline__ void ll_store_val(uint64_t* p, double v, uint32_t flag) { ll_store_f64(p, v, flag); }
 __device__ __forceinline__ void ll_store_val(uint64_t* p, float v, uint32_t flag) {
@@ -77,6 +90,127 @@ template <> __device__ __forceinline__ double ll_load_val<double>(const uint64_t
 template <> __device__ __forceinline__ float ll_load_val<float>(const uint64_t* p, uint32_t flag, int* err) {
   return __uint_as_float(ll_load(p, flag, err));
 }
+
+// K values (value k at p + k * stride words) loaded with one combined wait:
+// every word is requested before any flag is checked, so a ready message costs
+// one round trip instead of K.  valid[k] = false skips value k.
+template <typename T, int K>
+__device__ __forceinline__ void ll_load_many(const uint64_t* p, int64_t stride, const bool* valid, uint32_t flag,
+                                             int* err, T* out) {
+  constexpr int LW = sizeof(T) == 8 ? 2 : 1;
+  long long spins = 0;
+  while (true) {
+    uint64_t w[K][LW];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int h = 0; h < LW; ++h)
+        w[k][h] = valid[k] ? __hip_atomic_load(const_cast<uint64_t*>(p + k * stride + h), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT)
+                           : ((uint64_t)flag << 32);
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int h = 0; h < LW; ++h) ok = ok && ((uint32_t)(w[k][h] >> 32) == flag);
+    if (ok) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if constexpr (LW == 2)
+          out[k] = __longlong_as_double((long long)(((w[k][1] & 0xffffffffull) << 32) | (w[k][0] & 0xffffffffull)));
+        else
+          out[k] = __uint_as_float((uint32_t)w[k][0]);
+      }
+      return;
+    }
+    ++spins;
+    if ((spins & 1023) == 0) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[k] = (T)0;
+        return;
+      }
+      if (spins > (kSpinLimit >> 2)) {
+        atomicExch(err, (int)kErrSpinTimeout);
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[k] = (T)0;
+        return;
+      }
+    }
+  }
+}
+
+// K values at arbitrary addresses, one combined wait (see ll_load_many).
+template <typename T, int K>
+__device__ __forceinline__ void ll_wait_vals(const uint64_t* const* ptr, const bool* valid, uint32_t flag, int* err,
+                                             T* out) {
+  constexpr int LW = sizeof(T) == 8 ? 2 : 1;
+  long long spins = 0;
+  while (true) {
+    uint64_t w[K][LW];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int h = 0; h < LW; ++h)
+        w[k][h] = valid[k] ? __hip_atomic_load(const_cast<uint64_t*>(ptr[k] + h), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT)
+                           : ((uint64_t)flag << 32);
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int h = 0; h < LW; ++h) ok = ok && ((uint32_t)(w[k][h] >> 32) == flag);
+    if (ok) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if constexpr (LW == 2)
+          out[k] = __longlong_as_double((long long)(((w[k][1] & 0xffffffffull) << 32) | (w[k][0] & 0xffffffffull)));
+        else
+          out[k] = __uint_as_float((uint32_t)w[k][0]);
+      }
+      return;
+    }
+    ++spins;
+    if ((spins & 1023) == 0) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || spins > (kSpinLimit >> 2)) {
+        if (spins > (kSpinLimit >> 2)) atomicExch(err, (int)kErrSpinTimeout);
+#pragma unroll
+        for (int k = 0; k < K; ++k) out[k] = (T)0;
+        return;
+      }
+    }
+  }
+}
+
+// N raw 32-bit payloads at p[0..N) with one combined wait.
+template <int N>
+__device__ __forceinline__ void ll_wait_words(const uint64_t* p, uint32_t flag, int* err, uint32_t* out) {
+  long long spins = 0;
+  while (true) {
+    uint64_t w[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+      w[k] = __hip_atomic_load(const_cast<uint64_t*>(p + k), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < N; ++k) ok = ok && ((uint32_t)(w[k] >> 32) == flag);
+    if (ok) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) out[k] = (uint32_t)w[k];
+      return;
+    }
+    ++spins;
+    if ((spins & 1023) == 0) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || spins > (kSpinLimit >> 2)) {
+        if (spins > (kSpinLimit >> 2)) atomicExch(err, (int)kErrSpinTimeout);
+#pragma unroll
+        for (int k = 0; k < N; ++k) out[k] = 0u;
+        return;
+      }
+    }
+  }
+}
+
 // words per value in a message
 template <typename T> struct LLWords { static constexpr int n = 2; };
 template <> struct LLWords<float> { static constexpr int n = 1; };

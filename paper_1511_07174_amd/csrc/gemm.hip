@@ -16,6 +16,10 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+#ifndef CDS_GEMM_SCHED
+#define CDS_GEMM_SCHED 1
+#endif
+
 namespace cds {
 
 namespace {
@@ -61,16 +65,19 @@ template <typename T>
 __device__ __forceinline__ T ldg_or_zero(const T* p, bool ok) { return ok ? *p : (T)0; }
 
 // ------------------------------------------------------------------------------------
-// Native-precision kernel (double: f64 MFMA; float: f32 MFMA)
+// Native-precision kernel (double: f64 MFMA; float: f32 MFMA).
+// VEC: 16-byte global loads (host checked the alignment of A, B and the leading
+// dimensions); edge vectors fall back to element loads with bounds checks.
 // ------------------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool VEC>
 __global__ void __launch_bounds__(NT, 2)
 gemm_native_kernel(GemmArgs<T> g) {
   if (g.guard && *g.guard != 0) return;
   constexpr int BK = GemmCfg<T, 0>::BK;
-  constexpr int PADM = BM + 4;  // row pitch in LDS (elements)
-  __shared__ T As[2][BK][PADM];
-  __shared__ T Bs[2][BK][PADM];
+  constexpr int PADM = BM + 4;  // row pitch in LDS (elements); PADM * sizeof(T) is a multiple of 16
+  constexpr int NV = VEC ? 16 / (int)sizeof(T) : 1;   // elements per global load
+  __shared__ __attribute__((aligned(16))) T As[2][BK][PADM];
+  __shared__ __attribute__((aligned(16))) T Bs[2][BK][PADM];
 
   const int b = blockIdx.y;
   const T* __restrict__ A = g.A + (size_t)b * g.strideA;
@@ -87,63 +94,116 @@ gemm_native_kernel(GemmArgs<T> g) {
   const int wave = tid >> 6;
   const int wr = (wave & 1) * 64, wc = (wave >> 1) * 64;
 
-  constexpr int A_PER = BM * BK / NT;  // elements per thread per tile
-  constexpr int B_PER = BK * BN / NT;
-  T ra[A_PER], rb[B_PER];
+  constexpr int A_PER = BM * BK / NT / NV;  // vectors per thread per tile
+  constexpr int B_PER = BK * BN / NT / NV;
+  T ra[A_PER][NV], rb[B_PER][NV];
 
+  // A tile (BM x BK): vectors run down a column (rows contiguous)
   auto load_tile = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < A_PER; ++r) {
-      int e = tid + r * NT;
-      int i = e % BM, kk = e / BM;
-      int gi = row0 + i, gk = k0 + kk;
-      ra[r] = ldg_or_zero(A + gi + (size_t)gk * g.lda, gi < g.m && gk < g.k);
+      const int e = tid + r * NT;
+      const int i = (e % (BM / NV)) * NV, kk = e / (BM / NV);
+      const int gi = row0 + i, gk = k0 + kk;
+      const T* p = A + gi + (size_t)gk * g.lda;
+      if (VEC && gk < g.k && gi + NV <= g.m) {
+        if constexpr (VEC) {
+          typedef T v_t __attribute__((ext_vector_type(NV)));
+          v_t v = *reinterpret_cast<const v_t*>(p);
+#pragma unroll
+          for (int t = 0; t < NV; ++t) ra[r][t] = v[t];
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < NV; ++t) ra[r][t] = ldg_or_zero(p + t, gi + t < g.m && gk < g.k);
+      }
     }
     if (!g.transB) {
+      // B(k, j) = B[k + j ldb]: vectors run along k inside a column
 #pragma unroll
       for (int r = 0; r < B_PER; ++r) {
-        int e = tid + r * NT;
-        int kk = e % BK, j = e / BK;
-        int gk = k0 + kk, gj = col0 + j;
-        rb[r] = ldg_or_zero(B + gk + (size_t)gj * g.ldb, gk < g.k && gj < g.n);
+        const int e = tid + r * NT;
+        const int kk = (e % (BK / NV)) * NV, j = e / (BK / NV);
+        const int gk = k0 + kk, gj = col0 + j;
+        const T* p = B + gk + (size_t)gj * g.ldb;
+        if (VEC && gj < g.n && gk + NV <= g.k) {
+          if constexpr (VEC) {
+            typedef T v_t __attribute__((ext_vector_type(NV)));
+            v_t v = *reinterpret_cast<const v_t*>(p);
+#pragma unroll
+            for (int t = 0; t < NV; ++t) rb[r][t] = v[t];
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < NV; ++t) rb[r][t] = ldg_or_zero(p + t, gk + t < g.k && gj < g.n);
+        }
       }
     } else {
+      // B(k, j) = B[j + k ldb]: vectors run along j
 #pragma unroll
       for (int r = 0; r < B_PER; ++r) {
-        int e = tid + r * NT;
-        int j = e % BN, kk = e / BN;
-        int gk = k0 + kk, gj = col0 + j;
-        rb[r] = ldg_or_zero(B + gj + (size_t)gk * g.ldb, gk < g.k && gj < g.n);
+        const int e = tid + r * NT;
+        const int j = (e % (BN / NV)) * NV, kk = e / (BN / NV);
+        const int gk = k0 + kk, gj = col0 + j;
+        const T* p = B + gj + (size_t)gk * g.ldb;
+        if (VEC && gk < g.k && gj + NV <= g.n) {
+          if constexpr (VEC) {
+            typedef T v_t __attribute__((ext_vector_type(NV)));
+            v_t v = *reinterpret_cast<const v_t*>(p);
+#pragma unroll
+            for (int t = 0; t < NV; ++t) rb[r][t] = v[t];
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < NV; ++t) rb[r][t] = ldg_or_zero(p + t, gk < g.k && gj + t < g.n);
+        }
       }
     }
   };
+  const T alpha = g.alpha;
   auto store_tile = [&](int buf) {
 #pragma unroll
     for (int r = 0; r < A_PER; ++r) {
-      int e = tid + r * NT;
-      As[buf][e / BM][e % BM] = ra[r];
+      const int e = tid + r * NT;
+      const int i = (e % (BM / NV)) * NV, kk = e / (BM / NV);
+#pragma unroll
+      for (int t = 0; t < NV; ++t) As[buf][kk][i + t] = alpha * ra[r][t];
     }
     if (!g.transB) {
 #pragma unroll
       for (int r = 0; r < B_PER; ++r) {
-        int e = tid + r * NT;
-        Bs[buf][e % BK][e / BK] = rb[r];
+        const int e = tid + r * NT;
+        const int kk = (e % (BK / NV)) * NV, j = e / (BK / NV);
+#pragma unroll
+        for (int t = 0; t < NV; ++t) Bs[buf][kk + t][j] = rb[r][t];
       }
     } else {
 #pragma unroll
       for (int r = 0; r < B_PER; ++r) {
-        int e = tid + r * NT;
-        Bs[buf][e / BN][e % BN] = rb[r];
+        const int e = tid + r * NT;
+        const int j = (e % (BN / NV)) * NV, kk = e / (BN / NV);
+#pragma unroll
+        for (int t = 0; t < NV; ++t) Bs[buf][kk][j + t] = rb[r][t];
       }
     }
   };
 
+  // The accumulators start from C (loaded together with the first A/B tiles, so
+  // the read overlaps the prologue) and alpha is applied to the staged A
+  // operand (exact for alpha = -1), which leaves a store-only epilogue.
   typedef typename std::conditional<std::is_same<T, double>::value, d4, f4>::type acc_t;
   acc_t acc[4][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = (acc_t){0, 0, 0, 0};
+    for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = std::is_same<T, double>::value ? (lane / 16 + 4 * v) : (4 * (lane / 16) + v);
+        const int gi = row0 + wr + mi * 16 + r;
+        const int gj = col0 + wc + ni * 16 + (lane & 15);
+        acc[mi][ni][v] = (gi < g.m && gj < g.n && (!g.lower || gi >= gj)) ? C[gi + (size_t)gj * g.ldc] : (T)0;
+      }
 
   const int ktiles = (g.k + BK - 1) / BK;
   load_tile(0);
@@ -152,28 +212,46 @@ gemm_native_kernel(GemmArgs<T> g) {
   for (int kt = 0; kt < ktiles; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < ktiles) load_tile((kt + 1) * BK);
+    // fragments of k-step s + 1 are read from LDS while the MFMAs of step s run
+    T af[2][4], bf[2][4];
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      T af[4], bf[4];
+    for (int mi = 0; mi < 4; ++mi) af[0][mi] = As[buf][lane / 16][wr + mi * 16 + (lane & 15)];
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi) af[mi] = As[buf][kk + lane / 16][wr + mi * 16 + (lane & 15)];
+    for (int ni = 0; ni < 4; ++ni) bf[0][ni] = Bs[buf][lane / 16][wc + ni * 16 + (lane & 15)];
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni) bf[ni] = Bs[buf][kk + lane / 16][wc + ni * 16 + (lane & 15)];
+    for (int s = 0; s < BK / 4; ++s) {
+      const int cur = s & 1, nxt = cur ^ 1;
+      if (s + 1 < BK / 4) {
+#pragma unroll
+        for (int mi = 0; mi < 4; ++mi) af[nxt][mi] = As[buf][(s + 1) * 4 + lane / 16][wr + mi * 16 + (lane & 15)];
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni) bf[nxt][ni] = Bs[buf][(s + 1) * 4 + lane / 16][wc + ni * 16 + (lane & 15)];
+      }
 #pragma unroll
       for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni) {
           if constexpr (std::is_same<T, double>::value)
-            acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
+            acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[cur][mi], bf[cur][ni], acc[mi][ni], 0, 0, 0);
           else
-            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
+            acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[cur][mi], bf[cur][ni], acc[mi][ni], 0, 0, 0);
         }
+#if CDS_GEMM_SCHED
+      // spread the next step's 8 fragment reads between this step's 16 MFMAs
+      if (s + 1 < BK / 4) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // 2 MFMA
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // 1 LDS read
+        }
+      }
+#endif
     }
     if (kt + 1 < ktiles) store_tile(buf ^ 1);
     __syncthreads();
   }
 
-  // epilogue: C += alpha * acc
+  // epilogue: store only
 #pragma unroll
   for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
@@ -183,10 +261,7 @@ gemm_native_kernel(GemmArgs<T> g) {
         int r = std::is_same<T, double>::value ? (lane / 16 + 4 * v) : (4 * (lane / 16) + v);
         int gi = row0 + wr + mi * 16 + r;
         int gj = col0 + wc + ni * 16 + (lane & 15);
-        if (gi < g.m && gj < g.n && (!g.lower || gi >= gj)) {
-          T* p = C + gi + (size_t)gj * g.ldc;
-          *p = *p + g.alpha * acc[mi][ni][v];
-        }
+        if (gi < g.m && gj < g.n && (!g.lower || gi >= gj)) C[gi + (size_t)gj * g.ldc] = acc[mi][ni][v];
       }
 }
 
@@ -327,15 +402,24 @@ hipError_t launch_gemm(const GemmArgs<T>& g, int batch, int mode, hipStream_t s)
   int tiles_m = (g.m + BM - 1) / BM, tiles_n = (g.n + BN - 1) / BN;
   int tiles = g.lower ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
   dim3 grid(tiles, batch);
-  if constexpr (std::is_same<T, double>::value) {
-    hipLaunchKernelGGL(gemm_native_kernel<double>, grid, dim3(NT), 0, s, g);
-  } else {
-    if (mode == 1)
-      hipLaunchKernelGGL(gemm_mixed_kernel<1>, grid, dim3(NT), 0, s, g);
-    else if (mode == 2)
-      hipLaunchKernelGGL(gemm_mixed_kernel<2>, grid, dim3(NT), 0, s, g);
+  // 16-byte loads need 16-byte aligned bases and leading dimensions that keep every column aligned
+  constexpr int nv = 16 / (int)sizeof(T);
+  const bool vec = ((uintptr_t)g.A % 16 == 0) && ((uintptr_t)g.B % 16 == 0) && (g.lda % nv == 0) &&
+                   (g.ldb % nv == 0) && (g.strideA % nv == 0) && (g.strideB % nv == 0);
+  if (mode == 0) {
+    if (vec)
+      hipLaunchKernelGGL((gemm_native_kernel<T, true>), grid, dim3(NT), 0, s, g);
     else
-      hipLaunchKernelGGL(gemm_native_kernel<float>, grid, dim3(NT), 0, s, g);
+      hipLaunchKernelGGL((gemm_native_kernel<T, false>), grid, dim3(NT), 0, s, g);
+  } else {
+    if constexpr (std::is_same<T, float>::value) {
+      if (mode == 1)
+        hipLaunchKernelGGL(gemm_mixed_kernel<1>, grid, dim3(NT), 0, s, g);
+      else
+        hipLaunchKernelGGL(gemm_mixed_kernel<2>, grid, dim3(NT), 0, s, g);
+    } else {
+      return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }

@@ -4,11 +4,13 @@
 #include <stdint.h>
 #include <stddef.h>
 #include <type_traits>
+#include <vector>
 #include "../../include/cds.h"
 
 namespace cds {
 
-// C += alpha * A * op(B); A m x k, op(B) k x n, all column-major.
+// C += alpha * A * op(B); A m x k, op(B) k x n, all column-major.  The native-precision
+// kernel applies alpha to A (exact for the alpha = -1 of every caller).
 // transB = 1: op(B) = B^T with B stored n x k (ldb).
 // lower = 1: only C(i, j) with i >= j is computed and written (m == n).
 // For the FP16 operand mode, scale_exp[b] (device, may be null) is the power of
@@ -29,6 +31,26 @@ struct GemmArgs {
 template <typename T>
 hipError_t launch_gemm(const GemmArgs<T>& g, int batch, int mode, hipStream_t s);
 
+// Optional per-launch timing (events around launches of a kernel class).
+struct KTimer {
+  struct Rec { int kc; hipEvent_t a, b; double flops, bytes; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t next();
+  void reset();
+  ~KTimer();
+};
+
+// RAII scope: records an event before and after the launches made inside it.
+struct KScope {
+  KTimer* t;
+  hipStream_t s;
+  size_t idx;
+  KScope(KTimer* timer, int kc, hipStream_t stream, double flops, double bytes);
+  ~KScope();
+};
+
 // Execution context shared by the drivers.
 struct Ctx {
   hipStream_t s0;          // caller's stream
@@ -41,7 +63,7 @@ struct Ctx {
   int lookahead;
   int leaf;
   int panel_wgs;
-  int tune_getrf_nb_d, tune_getrf_nb_s, tune_potrf_nb_d, tune_potrf_nb_s;  // resolved per call
+  KTimer* timer;           // null unless kernel timing is on
 };
 
 // Sizes of the workspace regions (bytes), shared by bufferSize queries and drivers.

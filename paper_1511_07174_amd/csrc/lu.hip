@@ -26,7 +26,7 @@ namespace cds {
 namespace {
 
 constexpr int PNT = 256;    // threads (= rows) per panel workgroup
-constexpr int PCH = 64;     // column chunk of the in-panel update
+constexpr int PCH = 224;    // column chunk of the in-panel update (the whole right part for nb <= 256)
 
 template <typename T>
 struct PanelArgs {
@@ -55,44 +55,45 @@ struct SlotLayout {
   __host__ __device__ int64_t sw(int par, int e) const { return 2 * cs_par() + par * sw_par() + (int64_t)e * jb * LLW; }
 };
 
-// Column-step exchange, executed by wave 0 of every panel workgroup.
+// Column-step exchange, executed by wave 0 of every panel workgroup: this
+// workgroup's best candidate (from the per-wave results) is published with its
+// row, then every workgroup's header is read and the global pivot agreed on.
+// lf holds the workgroup's rows of the leaf (row-major, pitch W + 1).
 template <typename T, int W>
-__device__ __noinline__ void colstep_exchange(uint64_t* slots, SlotLayout<T, W> L, int g, int wl, int j, int par,
-                                              uint32_t flag, const T* red_mag, const int* red_row,
-                                              T (*cand)[W], const T* jrow_l, T* prow, T* jrow, int* s_p, int* err) {
+__device__ __forceinline__ void colstep_exchange(uint64_t* slots, const SlotLayout<T, W>& L, int g, int wl, int j,
+                                                 int par, uint32_t flag, const T* red_mag, const int* red_row,
+                                                 const T (*lf)[W + 1], T* prow, T* jrow, int* s_p, int* err) {
   constexpr int LLW = LLWords<T>::n;
   const int lane = lane_id();
-  // this workgroup's candidate
   T mag = lane < 4 ? red_mag[lane] : (T)-1;
   int row = lane < 4 ? red_row[lane] : 0x7fffffff;
-  int wv = lane;
-  {
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-      T om = shfl_xor(mag, m);
-      int orow = shfl_xor(row, m);
-      int owv = shfl_xor(wv, m);
-      bool take = (om > mag) || (om == mag && orow < row);
-      mag = take ? om : mag;
-      row = take ? orow : row;
-      wv = take ? owv : wv;
-    }
+  for (int m = 32; m >= 1; m >>= 1) {
+    T om = shfl_xor(mag, m);
+    int orow = shfl_xor(row, m);
+    bool take = (om > mag) || (om == mag && orow < row);
+    mag = take ? om : mag;
+    row = take ? orow : row;
   }
-  // publish header and candidate row
   uint64_t* hdr = slots + L.hdr(par, g);
   if (lane == 0) {
     ll_store_val(hdr, mag, flag);
     ll_store(hdr + LLW, (uint32_t)row, flag);
   }
-  if (mag >= (T)0 && lane < wl) ll_store_val(slots + L.cand(par, g) + lane * LLW, cand[wv][lane], flag);
-  if (j / PNT == g && lane < wl) ll_store_val(slots + L.rowj(par) + lane * LLW, jrow_l[lane], flag);
-  // gather all headers
+  if (mag >= (T)0 && lane < wl) ll_store_val(slots + L.cand(par, g) + lane * LLW, lf[row - g * PNT][lane], flag);
+  if (j / PNT == g && lane < wl) ll_store_val(slots + L.rowj(par) + lane * LLW, lf[j - g * PNT][lane], flag);
+  // every workgroup's header (one combined wait per lane)
   T bm = (T)-1;
   int br = 0x7fffffff;
   for (int i = lane; i < L.G; i += kWave) {
-    const uint64_t* h = slots + L.hdr(par, i);
-    T mi = ll_load_val<T>(h, flag, err);
-    int ri = (int)ll_load(h + LLW, flag, err);
+    uint32_t wv3[LLW + 1];
+    ll_wait_words<LLW + 1>(slots + L.hdr(par, i), flag, err, wv3);
+    T mi;
+    if constexpr (LLW == 2)
+      mi = __longlong_as_double((long long)(((uint64_t)wv3[1] << 32) | (uint64_t)wv3[0]));
+    else
+      mi = __uint_as_float(wv3[0]);
+    const int ri = (int)wv3[LLW];
     bool take = (mi > bm) || (mi == bm && ri < br);
     bm = take ? mi : bm;
     br = take ? ri : br;
@@ -108,8 +109,12 @@ __device__ __noinline__ void colstep_exchange(uint64_t* slots, SlotLayout<T, W> 
   const int p = br;
   const int gp = p / PNT;
   if (lane < wl) {
-    prow[lane] = ll_load_val<T>(slots + L.cand(par, gp) + lane * LLW, flag, err);
-    if (p != j) jrow[lane] = ll_load_val<T>(slots + L.rowj(par) + lane * LLW, flag, err);
+    const uint64_t* ptr[2] = {slots + L.cand(par, gp) + lane * LLW, slots + L.rowj(par) + lane * LLW};
+    const bool valid[2] = {true, p != j};
+    T v[2];
+    ll_wait_vals<T, 2>(ptr, valid, flag, err, v);
+    prow[lane] = v[0];
+    if (p != j) jrow[lane] = v[1];
   }
   if (lane == 0) *s_p = p;
 }
@@ -173,10 +178,9 @@ __global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
   const int row = g * PNT + tid;
   const bool own = row < m;
 
+  __shared__ T lf[PNT][W + 1];      // this workgroup's rows of the current leaf
   __shared__ T red_mag[4];
   __shared__ int red_row[4];
-  __shared__ T cand[4][W];
-  __shared__ T jrow_l[W];
   __shared__ T prow[W];
   __shared__ T jrow[W];
   __shared__ int s_p;
@@ -184,105 +188,122 @@ __global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
   __shared__ int s_piv[W];
   __shared__ int s_dst[3 * W], s_src[3 * W];
   __shared__ int s_ne;
-  __shared__ T Ubuf[W][PCH + 1];
+  __shared__ T Ubuf[W][PCH + 16];
 
-  T a[W];
   int leafc = 0;
   for (int c0 = 0; c0 < jb; c0 += W, ++leafc) {
     const int wl = min(W, jb - c0);
     const bool act = own && row >= c0;
+    {
+      T v[W];
 #pragma unroll
-    for (int cc = 0; cc < W; ++cc) a[cc] = (act && cc < wl) ? A[row + (size_t)(c0 + cc) * lda] : (T)0;
-
+      for (int cc = 0; cc < W; ++cc) v[cc] = (act && cc < wl) ? A[row + (size_t)(c0 + cc) * lda] : (T)0;
 #pragma unroll
-    for (int cc = 0; cc < W; ++cc) {
-      if (cc < wl) {
-        const int j = c0 + cc;
-        const int par = j & 1;
-        const uint32_t flag = (uint32_t)(P.k + j + 1);
-        const bool cand_ok = own && row >= j;
-        T mag = cand_ok ? fabs(a[cc]) : (T)-1;
-        int r = cand_ok ? row : 0x7fffffff;
-        wave_argmax(mag, r);
-        if (cand_ok && row == r) {
+      for (int cc = 0; cc < W; ++cc) lf[tid][cc] = v[cc];
+    }
+    for (int cc = 0; cc < wl; ++cc) {
+      const int j = c0 + cc;
+      const int par = j & 1;
+      const uint32_t flag = (uint32_t)(P.k + j + 1);
+      const bool cand_ok = own && row >= j;
+      T mag = cand_ok ? fabs(lf[tid][cc]) : (T)-1;
+      int r = cand_ok ? row : 0x7fffffff;
+      wave_argmax(mag, r);
+      if (lane == 0) { red_mag[wave] = mag; red_row[wave] = r; }
+      __syncthreads();
+      if (wave == 0)
+        colstep_exchange<T, W>(slots, L, g, wl, j, par, flag, red_mag, red_row, lf, prow, jrow, &s_p, P.err);
+      __syncthreads();
+      const int p = s_p;
+      T pr[W];
 #pragma unroll
-          for (int c2 = 0; c2 < W; ++c2) cand[wave][c2] = a[c2];
-        }
-        if (lane == 0) { red_mag[wave] = mag; red_row[wave] = r; }
-        if (own && row == j) {
+      for (int c2 = 0; c2 < W; ++c2) pr[c2] = prow[c2];
+      const T piv = prow[cc];
+      if (own && (row == j || row == p)) {
+        // interchange: row j takes the pivot row, row p the old row j
 #pragma unroll
-          for (int c2 = 0; c2 < W; ++c2) jrow_l[c2] = a[c2];
-        }
-        __syncthreads();
-        if (wave == 0)
-          colstep_exchange<T, W>(slots, L, g, wl, j, par, flag, red_mag, red_row, cand, jrow_l, prow, jrow, &s_p, P.err);
-        __syncthreads();
-        const int p = s_p;
-        const T piv = prow[cc];
-        if (own && row == j) {
+        for (int c2 = 0; c2 < W; ++c2)
+          if (c2 < wl) lf[tid][c2] = (row == j) ? pr[c2] : jrow[c2];
+      }
+      if (own && row > j && piv != (T)0) {
+        const T lmul = lf[tid][cc] / piv;
 #pragma unroll
-          for (int c2 = 0; c2 < W; ++c2) a[c2] = prow[c2];
-        } else if (own && row == p) {
-#pragma unroll
-          for (int c2 = 0; c2 < W; ++c2) a[c2] = jrow[c2];
-        }
-        if (own && row > j && piv != (T)0) {
-          const T l = a[cc] / piv;
-          a[cc] = l;
-#pragma unroll
-          for (int c2 = cc + 1; c2 < W; ++c2) a[c2] = (c2 < wl) ? (a[c2] - l * prow[c2]) : a[c2];
-        }
-        if (tid < W) L11[cc][tid] = prow[tid];
-        if (tid == 0) {
-          s_piv[cc] = p;
-          if (g == 0) {
-            ipiv[j] = P.k + p + 1;
-            if (piv == (T)0) atomicCAS(P.info + b, 0, P.k + j + 1);
-          }
-        }
+        for (int c2 = 0; c2 < W; ++c2)
+          if (c2 > cc && c2 < wl) lf[tid][c2] = lf[tid][c2] - lmul * pr[c2];
+        lf[tid][cc] = lmul;
+      }
+      if (tid < W) L11[cc][tid] = prow[tid];
+      if (tid == 0) {
+        s_piv[cc] = p;
+        // a zero pivot is recorded at once (rare); ipiv is written once per leaf so that no
+        // global store is outstanding at the next barrier
+        if (g == 0 && piv == (T)0) atomicCAS(P.info + b, 0, P.k + j + 1);
       }
     }
     // write back the leaf columns
     if (act) {
-#pragma unroll
-      for (int cc = 0; cc < W; ++cc)
-        if (cc < wl) A[row + (size_t)(c0 + cc) * lda] = a[cc];
+      for (int cc = 0; cc < wl; ++cc) A[row + (size_t)(c0 + cc) * lda] = lf[tid][cc];
     }
     __syncthreads();
     if (wave == 0) compose_leaf<W>(s_piv, c0, wl, s_dst, s_src, &s_ne);
     __syncthreads();
+    if (g == 0 && tid < wl) ipiv[c0 + tid] = P.k + s_piv[tid] + 1;
     const int ne = s_ne;
     const int spar = leafc & 1;
     const uint32_t sflag = (uint32_t)(P.k + c0 + 1);
     const int nv = jb - wl;   // non-leaf columns of the panel
-    // record the moves for the trailing/left interchange kernel
     if (g == 0) {
-      for (int e = tid; e < 3 * W; e += PNT) {
-        // entries with src == dst are recorded too (harmless), count covers all
-        if (e < ne) pairs[leafc * 3 * W + e] = make_int2(s_dst[e] + P.k, s_src[e] + P.k);
-      }
+      for (int e = tid; e < ne; e += PNT) pairs[leafc * 3 * W + e] = make_int2(s_dst[e] + P.k, s_src[e] + P.k);
       if (tid == 0) pair_cnt[leafc] = ne;
     }
     if (nv > 0) {
-      // publish rows this workgroup is the source of
-      for (int e = 0; e < ne; ++e) {
-        const int src = s_src[e];
-        if (src / PNT != g) continue;
-        uint64_t* sw = slots + L.sw(spar, e);
-        for (int idx = tid; idx < nv; idx += PNT) {
-          const int col = idx < c0 ? idx : idx + wl;
-          ll_store_val(sw + (int64_t)idx * LLW, A[src + (size_t)col * lda], sflag);
+      // publish the rows this workgroup is the source of (columns outside the leaf); items
+      // (entry, column) are flattened and handled in batches so that the loads overlap
+      {
+        constexpr int SB8 = 8;
+        const int total = ne * nv;
+        for (int base = 0; base < total; base += PNT * SB8) {
+          T v[SB8];
+          int64_t off[SB8];
+          bool ok[SB8];
+#pragma unroll
+          for (int q = 0; q < SB8; ++q) {
+            const int it = base + q * PNT + tid;
+            const int e = it / max(nv, 1), idx = it - e * nv;
+            ok[q] = it < total && (s_src[min(e, ne - 1)] / PNT == g);
+            const int col = idx < c0 ? idx : idx + wl;
+            off[q] = ok[q] ? (int64_t)L.sw(spar, e) + (int64_t)idx * LLW : 0;
+            v[q] = ok[q] ? A[s_src[e] + (size_t)col * lda] : (T)0;
+          }
+#pragma unroll
+          for (int q = 0; q < SB8; ++q)
+            if (ok[q]) ll_store_val(slots + off[q], v[q], sflag);
         }
       }
       __syncthreads();
       // move rows into the destinations this workgroup owns
-      for (int e = 0; e < ne; ++e) {
-        const int dst = s_dst[e], src = s_src[e];
-        if (dst / PNT != g || dst == src) continue;
-        const uint64_t* sw = slots + L.sw(spar, e);
-        for (int idx = tid; idx < nv; idx += PNT) {
-          const int col = idx < c0 ? idx : idx + wl;
-          A[dst + (size_t)col * lda] = ll_load_val<T>(sw + (int64_t)idx * LLW, sflag, P.err);
+      {
+        constexpr int SB8 = 8;
+        const int total = ne * nv;
+        for (int base = 0; base < total; base += PNT * SB8) {
+          const uint64_t* ptr[SB8];
+          bool ok[SB8];
+          size_t dsto[SB8];
+          T v[SB8];
+#pragma unroll
+          for (int q = 0; q < SB8; ++q) {
+            const int it = base + q * PNT + tid;
+            const int e = it / max(nv, 1), idx = it - e * nv;
+            const int ec = min(e, ne - 1);
+            ok[q] = it < total && (s_dst[ec] / PNT == g) && s_dst[ec] != s_src[ec];
+            const int col = idx < c0 ? idx : idx + wl;
+            ptr[q] = slots + L.sw(spar, ec) + (int64_t)idx * LLW;
+            dsto[q] = ok[q] ? (size_t)s_dst[ec] + (size_t)col * lda : 0;
+          }
+          ll_wait_vals<T, SB8>(ptr, ok, sflag, P.err, v);
+#pragma unroll
+          for (int q = 0; q < SB8; ++q)
+            if (ok[q]) A[dsto[q]] = v[q];
         }
       }
       __syncthreads();
@@ -290,10 +311,24 @@ __global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
       const int c1 = c0 + wl;
       for (int x0 = c1; x0 < jb; x0 += PCH) {
         const int cw = min(PCH, jb - x0);
-        for (int idx = tid; idx < wl * cw; idx += PNT) {
-          const int cc = idx / cw, x = idx % cw;
-          const int col = x0 + x;
-          Ubuf[cc][x] = ll_load_val<T>(slots + L.sw(spar, cc) + (int64_t)(col - wl) * LLW, sflag, P.err);
+        const int total = wl * cw;
+        for (int base = 0; base < total; base += PNT * 8) {
+          const uint64_t* ptr[8];
+          bool valid[8];
+          T v[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int idx = base + q * PNT + tid;
+            valid[q] = idx < total;
+            const int cc = valid[q] ? idx / cw : 0, x = valid[q] ? idx % cw : 0;
+            ptr[q] = slots + L.sw(spar, cc) + (int64_t)(x0 + x - wl) * LLW;
+          }
+          ll_wait_vals<T, 8>(ptr, valid, sflag, P.err, v);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int idx = base + q * PNT + tid;
+            if (valid[q]) Ubuf[idx / cw][idx % cw] = v[q];
+          }
         }
         __syncthreads();
         if (tid < cw) {
@@ -310,18 +345,31 @@ __global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
           if (r / PNT == g) A[r + (size_t)(x0 + x) * lda] = Ubuf[cc][x];
         }
         if (own && row >= c1) {
-          for (int x = 0; x < cw; ++x) {
-            T* pa = A + row + (size_t)(x0 + x) * lda;
-            T v = *pa;
+          // batches of GX columns, the loads of the next batch in flight during this one
+          constexpr int GX = 8;
+          T cur[GX], nxt[GX];
 #pragma unroll
-            for (int cc = 0; cc < W; ++cc)
-              if (cc < wl) v -= a[cc] * Ubuf[cc][x];
-            *pa = v;
+          for (int q = 0; q < GX; ++q) cur[q] = (q < cw) ? A[row + (size_t)(x0 + q) * lda] : (T)0;
+          for (int x = 0; x < cw; x += GX) {
+#pragma unroll
+            for (int q = 0; q < GX; ++q)
+              nxt[q] = (x + GX + q < cw) ? A[row + (size_t)(x0 + x + GX + q) * lda] : (T)0;
+            for (int cc = 0; cc < wl; ++cc) {
+              const T lc = lf[tid][cc];
+#pragma unroll
+              for (int q = 0; q < GX; ++q) cur[q] -= lc * Ubuf[cc][x + q];
+            }
+#pragma unroll
+            for (int q = 0; q < GX; ++q)
+              if (x + q < cw) A[row + (size_t)(x0 + x + q) * lda] = cur[q];
+#pragma unroll
+            for (int q = 0; q < GX; ++q) cur[q] = nxt[q];
           }
         }
         __syncthreads();
       }
     }
+    __syncthreads();
   }
 }
 
@@ -364,46 +412,78 @@ __global__ void __launch_bounds__(256) laswp_kernel(T* A0, int64_t lda, int64_t 
 }
 
 // U12 = L11^{-1} A12: L11 = jb x jb unit lower at L (ld lda), A12 = jb x ncols at X (ld lda).
-// Each workgroup solves CW columns held in LDS, 16-row blocks.
-template <typename T>
+// Each workgroup solves CW columns held in LDS, 16-row blocks.  The 16 columns of
+// L below each diagonal block are staged in LDS, the next block's are prefetched
+// into registers while the current one is used; the 16 x 16 diagonal solve keeps
+// the column in registers.
+template <typename T, int PRE>
 __global__ void __launch_bounds__(256) trsm_llnu_kernel(const T* L0, T* X0, int64_t lda, int64_t strideA, int jb,
                                                         int ncols, int CW) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* X = reinterpret_cast<T*>(smem_raw);   // [jb][CW+1]
+  constexpr int RB = 16;
+  const int P = CW + 1;
+  T* X = reinterpret_cast<T*>(smem_raw);                 // [jb][CW+1]
+  T* Lb = X + (size_t)jb * P;                            // [jb][RB+1]
   const int b = blockIdx.y;
   const T* L = L0 + (size_t)b * strideA;
   T* Xg = X0 + (size_t)b * strideA;
   const int c0 = blockIdx.x * CW;
   const int cw = min(CW, ncols - c0);
   const int tid = threadIdx.x;
-  const int P = CW + 1;
   for (int idx = tid; idx < jb * cw; idx += 256) {
     const int c = idx / jb, r = idx % jb;
     X[r * P + c] = Xg[r + (size_t)(c0 + c) * lda];
   }
-  __syncthreads();
-  constexpr int RB = 16;
+  // prefetch of the next block of L (rows [r0, jb), 16 columns): PRE * 256 >= 16 * jb elements
+  T pre[PRE];
+  auto prefetch = [&](int r0) {
+    const int rows = jb - r0, rbk = min(RB, jb - r0);
+#pragma unroll
+    for (int u = 0; u < PRE; ++u) {
+      const int e = tid + 256 * u;
+      const int i = e % rows, t = e / rows;
+      pre[u] = (rows > 0 && t < rbk && e < rows * rbk) ? L[(r0 + i) + (size_t)(r0 + t) * lda] : (T)0;
+    }
+  };
+  prefetch(0);
   for (int r0 = 0; r0 < jb; r0 += RB) {
-    const int rb = min(RB, jb - r0);
-    // diagonal block: one thread per column
+    const int rb = min(RB, jb - r0), rows = jb - r0;
+    __syncthreads();   // previous block done with Lb; X loads complete on the first pass
+#pragma unroll
+    for (int u = 0; u < PRE; ++u) {
+      const int e = tid + 256 * u;
+      if (e < rows * rb) Lb[(e % rows) * (RB + 1) + e / rows] = pre[u];
+    }
+    if (r0 + RB < jb) prefetch(r0 + RB);
+    __syncthreads();
+    // diagonal block: one thread per column, the column in registers
     if (tid < cw) {
-      for (int i = 1; i < rb; ++i) {
-        T s = X[(r0 + i) * P + tid];
-        for (int t = 0; t < i; ++t) s -= L[(r0 + i) + (size_t)(r0 + t) * lda] * X[(r0 + t) * P + tid];
-        X[(r0 + i) * P + tid] = s;
+      T x[RB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) x[i] = (i < rb) ? X[(r0 + i) * P + tid] : (T)0;
+#pragma unroll
+      for (int i = 1; i < RB; ++i) {
+        T s = x[i];
+#pragma unroll
+        for (int t = 0; t < i; ++t) s -= Lb[i * (RB + 1) + t] * x[t];
+        x[i] = s;
       }
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+        if (i < rb) X[(r0 + i) * P + tid] = x[i];
     }
     __syncthreads();
-    // rows below
-    const int nbelow = jb - r0 - rb;
+    const int nbelow = rows - rb;
     for (int idx = tid; idx < nbelow * cw; idx += 256) {
-      const int r = r0 + rb + idx % nbelow, c = idx / nbelow;
-      T s = X[r * P + c];
-      for (int t = 0; t < rb; ++t) s -= L[r + (size_t)(r0 + t) * lda] * X[(r0 + t) * P + c];
-      X[r * P + c] = s;
+      const int rr = rb + idx % nbelow, c = idx / nbelow;
+      T s = X[(r0 + rr) * P + c];
+#pragma unroll
+      for (int t = 0; t < RB; ++t)
+        if (t < rb) s -= Lb[rr * (RB + 1) + t] * X[(r0 + t) * P + c];
+      X[(r0 + rr) * P + c] = s;
     }
-    __syncthreads();
   }
+  __syncthreads();
   for (int idx = tid; idx < jb * cw; idx += 256) {
     const int c = idx / jb, r = idx % jb;
     Xg[r + (size_t)(c0 + c) * lda] = X[r * P + c];
@@ -444,7 +524,7 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
     return CDS_SUCCESS;
   }
   if (nb <= 0) nb = default_nb(n);
-  nb = std::max(kLeaf, (nb / kLeaf) * kLeaf);
+  nb = std::min(512, std::max(kLeaf, (nb / kLeaf) * kLeaf));
   const int W = kLeaf;
   const int G = (n + PNT - 1) / PNT;
   const int jbmax = std::min(nb, n);
@@ -487,6 +567,9 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
     P.cnt_stride = nleaves;
     P.err = c.err;
     P.G = (n - k + PNT - 1) / PNT;
+    const double m = n - k;
+    KScope ks(c.timer, CDS_KC_PANEL, s, batch * (m * jb * jb - (double)jb * jb * jb / 3.0),
+              batch * 2.0 * m * jb * sizeof(T));
     hipLaunchKernelGGL((panel_kernel<T, kLeaf>), dim3(P.G, batch), dim3(PNT), 0, s, P);
     return hipGetLastError();
   };
@@ -499,7 +582,7 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
     int ncols = (hi1 - lo1) + (ce - cb);
     if (ncols > 0) {
       int blocks = std::min(4096, (ncols + 3) / 4);
-      // pair counts are laid out per matrix with stride nleaves; laswp reads [b*nleaves + l]
+      KScope ks(c.timer, CDS_KC_LASWP, s, 0.0, batch * 4.0 * sizeof(T) * jb * (double)ncols);
       hipLaunchKernelGGL((laswp_kernel<T, kLeaf>), dim3(blocks, batch), dim3(256), 0, s, A, lda, strideA, pr, pc,
                          pairs_stride, nleaves, nl, lo1, hi1, cb, ce);
       hipError_t e = hipGetLastError();
@@ -507,10 +590,17 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
     }
     if (ce > cb) {
       const int nc = ce - cb;
-      int CW = (int)std::max<int64_t>(8, std::min<int64_t>(64, 65536 / ((int64_t)(jb + 0) * sizeof(T))));
-      size_t sm = (size_t)jb * (CW + 1) * sizeof(T);
-      hipLaunchKernelGGL((trsm_llnu_kernel<T>), dim3((nc + CW - 1) / CW, batch), dim3(256), sm, s,
-                         (const T*)(A + k + (size_t)k * lda), A + k + (size_t)cb * lda, lda, strideA, jb, nc, CW);
+      // 16 columns per workgroup in FP64, 32 in FP32 (two workgroups per CU at jb = 256)
+      int CW = sizeof(T) == 8 ? 16 : 32;
+      size_t sm = ((size_t)jb * (CW + 1) + (size_t)jb * 17) * sizeof(T);
+      KScope* kt = new KScope(c.timer, CDS_KC_TRSM, s, batch * (double)jb * jb * nc, 0.0);
+      if (jb <= 256)
+        hipLaunchKernelGGL((trsm_llnu_kernel<T, 16>), dim3((nc + CW - 1) / CW, batch), dim3(256), sm, s,
+                           (const T*)(A + k + (size_t)k * lda), A + k + (size_t)cb * lda, lda, strideA, jb, nc, CW);
+      else
+        hipLaunchKernelGGL((trsm_llnu_kernel<T, 32>), dim3((nc + CW - 1) / CW, batch), dim3(256), sm, s,
+                           (const T*)(A + k + (size_t)k * lda), A + k + (size_t)cb * lda, lda, strideA, jb, nc, CW);
+      delete kt;
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
       const int mrem = n - k - jb;
@@ -531,6 +621,8 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
         ga.B = A + k + (size_t)cb * lda; ga.ldb = lda; ga.strideB = strideA;
         ga.C = A + (k + jb) + (size_t)cb * lda; ga.ldc = lda; ga.strideC = strideA;
         ga.alpha = (T)-1; ga.transB = 0; ga.lower = 0; ga.scale_exp = sc; ga.guard = nullptr;
+        KScope ks(c.timer, CDS_KC_UPDATE, s, batch * 2.0 * mrem * (double)nc * jb,
+                  batch * (double)sizeof(T) * (2.0 * mrem * nc + (double)mrem * jb + (double)jb * nc));
         e = launch_gemm<T>(ga, batch, mode, s);
         if (e != hipSuccess) return e;
       }

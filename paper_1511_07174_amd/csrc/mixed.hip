@@ -467,6 +467,8 @@ static cds_status_t refine(Ctx& c, const IrWs& w, int trans, int chol, int n, in
   const int max_iter = prm.max_iter;
   std::vector<int> h_active;
   for (int it = 0; it <= max_iter; ++it) {
+    KScope* ks = new KScope(c.timer, CDS_KC_RESIDUAL, s, 2.0 * batch * n * (double)n * nrhs,
+                            8.0 * batch * ((chol ? 0.5 : 1.0) * n * (double)n * nrhs + 3.0 * n * nrhs));
     if (!chol) {
       hipLaunchKernelGGL(residual_kernel, dim3(rblocks, batch), dim3(256), 0, s, A, lda, strideA, (const double*)X,
                          ldx, strideX, B, ldb, strideB, w.R, (int64_t)n, (int64_t)n * nrhs, n, nrhs, trans, w.rnorm,
@@ -475,6 +477,7 @@ static cds_status_t refine(Ctx& c, const IrWs& w, int trans, int chol, int n, in
       hipLaunchKernelGGL(residual_sym_kernel, dim3(rblocks), dim3(256), 0, s, A, lda, (const double*)X, ldx, B, ldb,
                          w.R, (int64_t)n, n, nrhs, w.rnorm, w.xnorm, (const int*)w.active);
     }
+    delete ks;
     if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
     hipLaunchKernelGGL(control_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, batch, nrhs, it, max_iter, prm.tol,
                        prm.success_tol, (const double*)w.anorm, w.rnorm, w.xnorm, w.st, res, w.active, info);

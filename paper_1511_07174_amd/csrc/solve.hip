@@ -225,6 +225,137 @@ __global__ void __launch_bounds__(TNT) trsv_kernel(TrsvArgs<T> a) {
   }
 }
 
+// Single right-hand side: every wave streams its quarter of each dependency
+// block straight from memory (DEPTH blocks of prefetch in registers) and waits
+// only for the flag+payload words of the solution values it needs, so the
+// dependency loop has no workgroup barrier.
+//   op N:  thread (i = lane, q = wave) accumulates M(r0+i, c0+16q..16q+15) . y
+//   op T:  thread (j = lane, q = wave) accumulates M(r0+16q+t, c0+j) * y_j for
+//          t < 16 and the rows are summed over the wave at the end.
+template <typename T, int DEPTH>
+__global__ void __launch_bounds__(TNT) trsv1_kernel(TrsvArgs<T> a) {
+  constexpr int LLW = LLWords<T>::n;
+  const int b = blockIdx.z;
+  if (a.active && a.active[b] == 0) return;
+  const T* M = a.M + (size_t)b * a.strideA;
+  T* Y = a.Y + (size_t)b * a.strideY;
+  uint64_t* slots = a.slots + (size_t)b * a.groups * a.slot_stride;
+  const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
+
+  __shared__ int s_ticket;
+  __shared__ T Ms[BS][BS + 1];
+  __shared__ T red[4][BS];
+  if (tid == 0) s_ticket = atomicAdd(a.tickets + (size_t)b * a.groups, 1);
+  __syncthreads();
+  const int lb = s_ticket;
+  if (lb >= a.nblk) return;
+  const int bk = a.upper ? (a.nblk - 1 - lb) : lb;
+  const int r0 = bk * BS, rb = min(BS, a.n - r0);
+  const int ndep = lb;
+  auto dep_block = [&](int d) { return a.upper ? (a.nblk - 1 - d) : d; };
+
+  // diagonal block into registers first (independent of everything else)
+  T dreg[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = tid + TNT * u;
+    const int fast = e & 63, slow = e >> 6;
+    int ii, jj;
+    if (!a.trans) { ii = fast; jj = slow; } else { ii = slow; jj = fast; }
+    dreg[u] = (ii < rb && jj < rb) ? mel(a, M, r0 + ii, r0 + jj) : (T)0;
+  }
+
+  T mbuf[DEPTH][16];
+  auto load = [&](T* dst, int cb) {
+    const int c0 = cb * BS;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      if (!a.trans) {
+        const int col = c0 + q * 16 + t;
+        dst[t] = (lane < rb && col < a.n) ? M[(r0 + lane) + (size_t)col * a.lda] : (T)0;
+      } else {
+        const int row = q * 16 + t, col = c0 + lane;
+        dst[t] = (row < rb && col < a.n) ? M[col + (size_t)(r0 + row) * a.lda] : (T)0;
+      }
+    }
+  };
+  T acc = (T)0;
+  T acct[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) acct[t] = (T)0;
+#pragma unroll
+  for (int s = 0; s < DEPTH; ++s)
+    if (s < ndep) load(mbuf[s], dep_block(s));
+  for (int d0 = 0; d0 < ndep; d0 += DEPTH) {
+#pragma unroll
+    for (int s = 0; s < DEPTH; ++s) {
+      const int d = d0 + s;
+      if (d < ndep) {
+        const int cb = dep_block(d), c0 = cb * BS;
+        const uint64_t* yb = slots + (size_t)cb * BS * LLW;
+        if (!a.trans) {
+          // lanes 0..15 fetch the wave's 16 solution values, shuffles broadcast them
+          const uint64_t* ptr[1] = {yb + (size_t)(q * 16 + (lane & 15)) * LLW};
+          const bool valid[1] = {lane < 16 && c0 + q * 16 + lane < a.n};
+          T y1[1];
+          ll_wait_vals<T, 1>(ptr, valid, a.flag, a.err, y1);
+#pragma unroll
+          for (int t = 0; t < 16; ++t) acc += mbuf[s][t] * __shfl(y1[0], t);
+        } else {
+          const uint64_t* ptr[1] = {yb + (size_t)lane * LLW};
+          const bool valid[1] = {c0 + lane < a.n};
+          T y[1];
+          ll_wait_vals<T, 1>(ptr, valid, a.flag, a.err, y);
+#pragma unroll
+          for (int t = 0; t < 16; ++t) acct[t] += mbuf[s][t] * y[0];
+        }
+        if (d + DEPTH < ndep) load(mbuf[s], dep_block(d + DEPTH));
+      }
+    }
+  }
+  if (!a.trans) {
+    red[q][lane] = acc;
+  } else {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const T v = wave_sum(acct[t]);
+      if (lane == 0) red[0][q * 16 + t] = v;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int e = tid + TNT * u;
+    const int fast = e & 63, slow = e >> 6;
+    if (!a.trans) Ms[fast][slow] = dreg[u]; else Ms[slow][fast] = dreg[u];
+  }
+  __syncthreads();
+  if (q == 0) {
+    const T dii = (lane < rb) ? Ms[lane][lane] : (T)1;
+    const T rdi = (T)1 / dii;   // reciprocals off the serial chain
+    T rhs = (lane < rb) ? Y[r0 + lane] : (T)0;
+    T val = a.trans ? (rhs - red[0][lane]) : (rhs - ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane])));
+    if (!a.upper) {
+      for (int t = 0; t < rb; ++t) {
+        T xt = __shfl(val, t);
+        if (!a.unit) xt = xt * __shfl(rdi, t);
+        if (lane == t) val = xt;
+        if (lane > t) val -= Ms[lane][t] * xt;
+      }
+    } else {
+      for (int t = rb - 1; t >= 0; --t) {
+        T xt = __shfl(val, t);
+        if (!a.unit) xt = xt * __shfl(rdi, t);
+        if (lane == t) val = xt;
+        if (lane < t) val -= Ms[lane][t] * xt;
+      }
+    }
+    if (lane < rb) {
+      ll_store_val(slots + ((size_t)bk * BS + lane) * LLW, val, a.flag);
+      Y[r0 + lane] = val;
+    }
+  }
+}
+
 template <typename T, int NR>
 hipError_t launch_trsv_nr(const TrsvArgs<T>& a, int batch, hipStream_t s) {
   dim3 grid(a.nblk, a.groups, batch);
@@ -324,7 +455,12 @@ cds_status_t getrs_core(Ctx& c, const GetrsCore<T, S>& g) {
     if (launch_fill_zero(slots, slot_b, s) != hipSuccess) return CDS_HIP_ERROR;
     if (launch_fill_i32(tickets, (int64_t)batch * groups, 0, s) != hipSuccess) return CDS_HIP_ERROR;
     hipError_t e;
-    if (nr == 1) e = launch_trsv_nr<T, 1>(a, batch, s);
+    KScope ks(c.timer, CDS_KC_TRSV, s, (double)batch * n * (double)n * nrhs,
+              (double)batch * sizeof(T) * ((double)n * n / 2.0 * groups + 2.0 * n * nrhs));
+    if (nr == 1) {
+      hipLaunchKernelGGL((trsv1_kernel<T, 4>), dim3(a.nblk, 1, batch), dim3(TNT), 0, s, a);
+      e = hipGetLastError();
+    }
     else if (nr == 8) e = launch_trsv_nr<T, 8>(a, batch, s);
     else e = launch_trsv_nr<T, 32>(a, batch, s);
     if (e != hipSuccess) return CDS_HIP_ERROR;

@@ -29,6 +29,33 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipEvent_t KTimer::next() {
+  if (used == pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    pool.push_back(e);
+  }
+  return pool[used++];
+}
+void KTimer::reset() {
+  recs.clear();
+  used = 0;
+}
+KTimer::~KTimer() {
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+KScope::KScope(KTimer* timer, int kc, hipStream_t stream, double flops, double bytes) : t(timer), s(stream), idx(0) {
+  if (!t) return;
+  hipEvent_t a = t->next(), b = t->next();
+  if (!a || !b) { t = nullptr; return; }
+  (void)hipEventRecord(a, s);
+  t->recs.push_back(KTimer::Rec{kc, a, b, flops, bytes});
+  idx = t->recs.size() - 1;
+}
+KScope::~KScope() {
+  if (t) (void)hipEventRecord(t->recs[idx].b, s);
+}
+
 hipError_t launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   int blocks = (int)std::min<int64_t>(1024, (count + 255) / 256);

@@ -1,0 +1,122 @@
+"""Autotuner for the library's tile and block sizes.
+
+Times candidate settings on the device, keeps the fastest per size bucket and
+persists a JSON table; ``load_table`` installs a table into a handle through
+``cds_tune_set``.  Tuned quantities:
+
+* ``getrf_nb`` (per dtype, per n bucket): block size of the blocked LU, from
+  {128, 256, 512};
+* ``potrf_nb``: same for Cholesky;
+* ``vbatch_tile`` (per n bucket): block-column width of the in-workgroup
+  Cholesky of the batched SPD solver, 16 or 32.
+
+Inputs are seeded synthetic matrices of the tuned sizes.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+
+import torch
+
+from . import cds
+from .cds import colmajor
+
+KEYS = {"getrf_nb": cds.TUNE_GETRF_NB, "potrf_nb": cds.TUNE_POTRF_NB, "vbatch_tile": cds.TUNE_VBATCH_TILE}
+DTYPES = {"f64": cds.R_64F, "f32": cds.R_32F}
+
+
+def _timeit(fn, reps=2):
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t)
+    return best
+
+
+def tune_getrf(sizes=(4096, 8192, 16384), dtypes=("f64", "f32"), candidates=(128, 256, 512), seed=0):
+    h = cds.handle()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    g = torch.Generator(device=dev).manual_seed(seed)
+    entries, timings = [], []
+    for dt in dtypes:
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        for n in sizes:
+            A = colmajor(torch.rand(n, n, generator=g, device=dev, dtype=tdt) * 2 - 1)
+            LU = torch.empty_like(A)
+            ipiv = torch.zeros(n, dtype=torch.int32, device=dev)
+            info = torch.zeros(1, dtype=torch.int32, device=dev)
+            best = None
+            for nb in candidates:
+                h.set_option(cds.OPT_NB, nb)
+
+                def run():
+                    LU.copy_(A)
+                    h.getrf_(LU, ipiv, info)
+                t = _timeit(run)
+                timings.append({"dtype": dt, "n": n, "nb": nb, "ms": t * 1e3})
+                if best is None or t < best[1]:
+                    best = (nb, t)
+            h.set_option(cds.OPT_NB, 0)
+            entries.append({"key": "getrf_nb", "dtype": dt, "n_max": n, "value": best[0]})
+            del A, LU
+    return entries, timings
+
+
+def tune_vbatched(buckets=((32, 128), (129, 256), (257, 512), (513, 1024)), count=96, seed=0):
+    """For each size bucket, time a batch of systems of that bucket with the 16- and 32-wide block
+    columns and keep the faster."""
+    h = cds.handle()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    entries, timings = [], []
+    from .solvers import solve_vbatched
+    for lo, hi in buckets:
+        systems = []
+        for _ in range(count):
+            n = int(torch.randint(lo, hi + 1, (1,), generator=g))
+            M = torch.rand(n, n, generator=g, dtype=torch.float64) * 2 - 1
+            A = M @ M.T / n + torch.eye(n, dtype=torch.float64)
+            B = torch.rand(n, 4, generator=g, dtype=torch.float64) * 2 - 1
+            systems.append((colmajor(A.to(dev)), colmajor(B.to(dev))))
+        best = None
+        for tile in (16, 32):
+            h.tune_clear()
+            h.tune_set(cds.TUNE_VBATCH_TILE, cds.R_32F, hi, tile)
+            t = _timeit(lambda: solve_vbatched(systems, nrhs=4))
+            timings.append({"bucket": [lo, hi], "tile": tile, "ms": t * 1e3})
+            if best is None or t < best[1]:
+                best = (tile, t)
+        entries.append({"key": "vbatch_tile", "dtype": "f32", "n_max": hi, "value": best[0]})
+    h.tune_clear()
+    return entries, timings
+
+
+def save_table(path, entries, timings=None):
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    table = {"arch": getattr(props, "gcnArchName", "gfx950"), "cus": props.multi_processor_count,
+             "entries": entries, "timings": timings or []}
+    with open(path, "w") as f:
+        json.dump(table, f, indent=1)
+    return path
+
+
+def load_table(path, handle=None):
+    """Install a saved table into a handle (default: the package's handle)."""
+    h = handle or cds.handle()
+    with open(path) as f:
+        table = json.load(f)
+    h.tune_clear()
+    for e in table["entries"]:
+        h.tune_set(KEYS[e["key"]], DTYPES[e["dtype"]], int(e["n_max"]), int(e["value"]))
+    return table
+
+
+def default_table_path():
+    return os.environ.get("CDS_TUNE_FILE", os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_gfx950.json"))

@@ -1,0 +1,208 @@
+"""GPU parity at the workload configurations: sampled/property checks at full
+size, the Householder kappa sweep with every factorization precision, the
+batched differentiable solve, and the uneven-size SPD batch (including
+capture into a graph and replay)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cds():
+    import paper_1511_07174_amd as m
+    oracle.build()
+    m.lib()
+    return m
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def to_dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.asfortranarray(a)).to(dev(), dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+# ------------------------------------------------------------------------ plain FP64 at full size (properties)
+@pytest.mark.parametrize("n", [4096])
+def test_getrf_4096_full_parity(cds, n):
+    """Full oracle comparison at n = 4096 (pivots, factors, backward error)."""
+    A, X, B = synth.uniform_system(n, 32, synth.SEED_LU[n])
+    LU, ipiv, info = cds.getrf(to_dev(A))
+    LUo, ipo, _ = oracle.getrf(A)
+    ph = host(ipiv)
+    mism = int(np.sum(ph != ipo))
+    assert mism == 0, mism
+    assert np.max(np.abs(host(LU) - LUo)) <= 1e-10 * np.max(np.abs(LUo))
+    Xd = cds.getrs(LU, ipiv, to_dev(B))
+    assert oracle.eta_inf(A, host(Xd), B) <= 1e-14
+
+
+@pytest.mark.parametrize("n", [8192, 16384])
+def test_getrf_large_properties(cds, n):
+    """Sizes the oracle cannot factor within a test: backward error with a double-double residual,
+    Freivalds probes of P A = L U, and the sampled rows of the oracle-independent relations."""
+    A, X, B = synth.uniform_system(n, 1, synth.SEED_LU[n])
+    Ad = to_dev(A)
+    LU, ipiv, info = cds.getrf(Ad)
+    assert int(info.item()) == 0
+    x = cds.getrs(LU, ipiv, to_dev(B[:, 0]))
+    LUh, ph = host(LU), host(ipiv)
+    assert oracle.eta_inf(A, host(x), B[:, 0]) <= 1e-14
+    assert oracle.freivalds_lu(A, LUh, ph, nprobe=4) <= 1e-13
+    # |l_ij| <= 1 (partial pivoting) and the pivots are a valid interchange sequence
+    assert np.max(np.abs(np.tril(LUh, -1))) <= 1.0
+    assert np.all(ph >= np.arange(1, n + 1)) and np.all(ph <= n)
+    assert cds.handle().device_error() == 0
+
+
+@pytest.mark.parametrize("n", [4096])
+def test_potrf_4096_parity(cds, n):
+    A, X, B = synth.spd_system(n, 32, synth.SEED_CHOL[n])
+    L, info = cds.potrf(to_dev(A))
+    Lo, info_o = oracle.potrf(A)
+    assert int(info.item()) == 0 and info_o == 0
+    assert np.max(np.abs(np.tril(host(L)) - np.tril(Lo))) <= 1e-12
+    Xd = cds.potrs(L, to_dev(B))
+    assert oracle.eta_inf(A, host(Xd), B) <= 1e-14
+
+
+# ------------------------------------------------------------------------ mixed precision, kappa sweep
+@pytest.mark.parametrize("kappa", [1e2, 1e4, 1e6])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_householder_sweep(cds, kappa, prec):
+    """Every result either converges (eta <= 1e-14, forward error within kappa * eta) or reports why it
+    stopped; the FP32 factorization must converge for every kappa here, and with the FP64 fallback
+    every precision converges."""
+    n = 2048
+    A, x_true, b, meta = synth.householder_system(n, kappa, seed=synth.householder_seed(8192, kappa))
+    xs = oracle.householder_solve(meta["vs_left"], meta["vs_right"], meta["sigma"], b)
+    X, res = cds.solve(to_dev(A), to_dev(b), precision=prec)
+    r = res[0]
+    x = host(X)
+    eta = oracle.eta_inf(A, x, b)
+    if r.converged:
+        assert eta <= 1e-14
+        assert np.max(np.abs(x - xs)) / np.max(np.abs(x)) <= kappa * 4 * n * 1e-14
+    else:
+        assert r.stop_reason in (2, 3, 4), r
+    if prec == "fp32":
+        assert r.converged, r
+    Xf, resf = cds.solve(to_dev(A), to_dev(b), precision=prec, params=cds.default_params(fallback=1))
+    assert resf[0].converged, resf[0]
+    assert oracle.eta_inf(A, host(Xf), b) <= 1e-14
+    if not r.converged:
+        assert resf[0].fell_back
+
+
+# ------------------------------------------------------------------------ batched differentiable solve
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_solve_gradients(cds, precision):
+    batch, n = 6, 256
+    g = synth.rng(synth.SEED_BATCH_GRAD)
+    As = [g.uniform(-1, 1, (n, n)) for _ in range(batch)]
+    bs = [g.uniform(-1, 1, n) for _ in range(batch)]
+    ws = [g.uniform(-1, 1, n) for _ in range(batch)]
+    Ad = torch.stack([to_dev(a) for a in As]).requires_grad_(True)
+    bd = torch.stack([to_dev(v) for v in bs]).requires_grad_(True)
+    x = cds.solve_ad(Ad, bd, precision)
+    loss = (x * torch.stack([to_dev(w) for w in ws])).sum()
+    loss.backward()
+    for i in range(batch):
+        xo = oracle.solve_refined(As[i], bs[i])
+        Abar_o, bbar_o = oracle.adjoint(As[i], xo, ws[i])
+        assert np.max(np.abs(host(x[i]) - xo)) <= 1e-10 * np.max(np.abs(xo))
+        assert oracle.eta_inf(As[i].T, host(bd.grad[i]), ws[i]) <= 1e-14
+        assert np.max(np.abs(host(bd.grad[i]) - bbar_o)) <= 1e-10 * np.max(np.abs(bbar_o))
+        assert np.max(np.abs(host(Ad.grad[i]) - Abar_o)) <= 1e-10 * np.max(np.abs(Abar_o))
+
+
+def test_gradcheck_fp64_small(cds):
+    """torch.autograd.gradcheck (central differences, FP64) through the library's solve."""
+    n = 24
+    g = synth.rng(synth.SEED_FD)
+    A = to_dev(g.uniform(-1, 1, (n, n)) + 3 * np.eye(n)).requires_grad_(True)
+    b = to_dev(g.uniform(-1, 1, n)).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda a, v: cds.solve_ad(a, v), (A, b), eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
+# ------------------------------------------------------------------------ batched uneven SPD
+def _vb_inputs(count, nmax, seed):
+    g = synth.rng(seed)
+    sizes = g.integers(32, nmax + 1, size=count)
+    host_sys, dev_sys = [], []
+    for n in sizes:
+        n = int(n)
+        M = g.uniform(-1, 1, (n, n))
+        A = M @ M.T / n + np.eye(n)
+        B = g.uniform(-1, 1, (n, 4))
+        host_sys.append((A, B))
+        dev_sys.append((to_dev(A), to_dev(B)))
+    return host_sys, dev_sys
+
+
+def test_vbatched_largest_first(cds):
+    host_sys, dev_sys = _vb_inputs(60, 700, 31)
+    order = np.argsort([-a.shape[0] for a, _ in host_sys], kind="stable")
+    Xs, res, t0, t1 = cds.solve_vbatched(dev_sys, nrhs=4, order=order)
+    t0h, t1h = host(t0), host(t1)
+    for (A, B), X, r, a0, a1 in zip(host_sys, Xs, res, t0h, t1h):
+        assert r.info == 0 and r.converged and r.iters <= 6, r
+        assert oracle.eta_inf(A, host(X), B) <= 1e-14
+        assert a1 > a0 > 0
+    assert cds.handle().device_error() == 0
+
+
+def test_vbatched_graph_replay(cds):
+    """One persistent launch captured in a graph; every replay equals the eager result bitwise."""
+    from paper_1511_07174_amd.cds import IR_RESULT_BYTES, decode_results
+    host_sys, dev_sys = _vb_inputs(40, 400, 32)
+    batch = len(dev_sys)
+    d = dev()
+    ns = torch.tensor([a.shape[0] for a, _ in dev_sys], dtype=torch.int32, device=d)
+    Ap = torch.tensor([a.data_ptr() for a, _ in dev_sys], dtype=torch.int64, device=d)
+    lda = torch.tensor([a.stride(1) for a, _ in dev_sys], dtype=torch.int64, device=d)
+    Bp = torch.tensor([b.data_ptr() for _, b in dev_sys], dtype=torch.int64, device=d)
+    ldb = torch.tensor([b.stride(1) for _, b in dev_sys], dtype=torch.int64, device=d)
+    Xs = [cds.colmajor(torch.zeros_like(b)) for _, b in dev_sys]
+    Xp = torch.tensor([x.data_ptr() for x in Xs], dtype=torch.int64, device=d)
+    ldx = torch.tensor([x.stride(1) for x in Xs], dtype=torch.int64, device=d)
+    res = torch.zeros(batch * IR_RESULT_BYTES, dtype=torch.uint8, device=d)
+    nmax = int(ns.max().item())
+    h = cds.handle()
+
+    def call():
+        h.posv_mixed_vbatched(batch, nmax, ns, Ap, lda, Bp, ldb, Xp, ldx, 4, res, device=d)
+
+    call()                                   # eager (also sizes the workspace before capture)
+    torch.cuda.synchronize()
+    eager = [x.clone() for x in Xs]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        call()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        call()
+    for rep in range(3):
+        for x in Xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for x, e in zip(Xs, eager):
+            assert torch.equal(x, e), "replay %d differs from the eager result" % rep
+    for (A, B), X, r in zip(host_sys, Xs, decode_results(res)):
+        assert r.converged and oracle.eta_inf(A, host(X), B) <= 1e-14
