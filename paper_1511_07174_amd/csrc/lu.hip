@@ -412,29 +412,31 @@ __global__ void __launch_bounds__(256) laswp_kernel(T* A0, int64_t lda, int64_t 
 }
 
 // U12 = L11^{-1} A12: L11 = jb x jb unit lower at L (ld lda), A12 = jb x ncols at X (ld lda).
-// Each workgroup solves CW columns held in LDS, 16-row blocks.  The 16 columns of
-// L below each diagonal block are staged in LDS, the next block's are prefetched
-// into registers while the current one is used; the 16 x 16 diagonal solve keeps
-// the column in registers.
+// A workgroup solves CW = 32 columns held in LDS, in 16-row blocks.  For each
+// block, the 16 columns of L below the diagonal block are staged in LDS (the
+// next block's prefetched into registers while the current one is used); the
+// 16 x 16 unit-lower diagonal solve runs with one column per lane; the update
+// of the rows below is a (rows x 16) x (16 x 32) product on MFMA 16x16x4 tiles
+// with operands read from LDS (the LDS operand rate would bound a VALU update).
 template <typename T, int PRE>
 __global__ void __launch_bounds__(256) trsm_llnu_kernel(const T* L0, T* X0, int64_t lda, int64_t strideA, int jb,
-                                                        int ncols, int CW) {
+                                                        int ncols) {
+  constexpr int CW = 32, RB = 16;
+  constexpr int PX = CW + 1;              // X pitch
+  constexpr int PL = RB + 1;              // Lb pitch
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  constexpr int RB = 16;
-  const int P = CW + 1;
-  T* X = reinterpret_cast<T*>(smem_raw);                 // [jb][CW+1]
-  T* Lb = X + (size_t)jb * P;                            // [jb][RB+1]
+  T* X = reinterpret_cast<T*>(smem_raw);  // [jb][PX]
+  T* Lb = X + (size_t)jb * PX;            // [jb][PL], rows relative to the block start
   const int b = blockIdx.y;
   const T* L = L0 + (size_t)b * strideA;
   T* Xg = X0 + (size_t)b * strideA;
   const int c0 = blockIdx.x * CW;
   const int cw = min(CW, ncols - c0);
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < jb * cw; idx += 256) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int idx = tid; idx < jb * CW; idx += 256) {
     const int c = idx / jb, r = idx % jb;
-    X[r * P + c] = Xg[r + (size_t)(c0 + c) * lda];
+    X[r * PX + c] = (c < cw) ? Xg[r + (size_t)(c0 + c) * lda] : (T)0;
   }
-  // prefetch of the next block of L (rows [r0, jb), 16 columns): PRE * 256 >= 16 * jb elements
   T pre[PRE];
   auto prefetch = [&](int r0) {
     const int rows = jb - r0, rbk = min(RB, jb - r0);
@@ -448,45 +450,67 @@ __global__ void __launch_bounds__(256) trsm_llnu_kernel(const T* L0, T* X0, int6
   prefetch(0);
   for (int r0 = 0; r0 < jb; r0 += RB) {
     const int rb = min(RB, jb - r0), rows = jb - r0;
-    __syncthreads();   // previous block done with Lb; X loads complete on the first pass
+    __syncthreads();   // the previous block is done with Lb and X
 #pragma unroll
     for (int u = 0; u < PRE; ++u) {
       const int e = tid + 256 * u;
-      if (e < rows * rb) Lb[(e % rows) * (RB + 1) + e / rows] = pre[u];
+      if (e < rows * rb) Lb[(e % rows) * PL + e / rows] = pre[u];
     }
     if (r0 + RB < jb) prefetch(r0 + RB);
     __syncthreads();
-    // diagonal block: one thread per column, the column in registers
-    if (tid < cw) {
+    // diagonal block: lane = column, rows in registers
+    if (wave == 0 && lane < CW) {
       T x[RB];
 #pragma unroll
-      for (int i = 0; i < RB; ++i) x[i] = (i < rb) ? X[(r0 + i) * P + tid] : (T)0;
+      for (int i = 0; i < RB; ++i) x[i] = (i < rb) ? X[(r0 + i) * PX + lane] : (T)0;
 #pragma unroll
       for (int i = 1; i < RB; ++i) {
         T s = x[i];
 #pragma unroll
-        for (int t = 0; t < i; ++t) s -= Lb[i * (RB + 1) + t] * x[t];
+        for (int t = 0; t < i; ++t) s -= Lb[i * PL + t] * x[t];
         x[i] = s;
       }
 #pragma unroll
       for (int i = 0; i < RB; ++i)
-        if (i < rb) X[(r0 + i) * P + tid] = x[i];
+        if (i < rb) X[(r0 + i) * PX + lane] = x[i];
     }
     __syncthreads();
+    // rows below: tiles of 16 rows x 16 columns, round-robin over the waves
     const int nbelow = rows - rb;
-    for (int idx = tid; idx < nbelow * cw; idx += 256) {
-      const int rr = rb + idx % nbelow, c = idx / nbelow;
-      T s = X[(r0 + rr) * P + c];
+    const int rtiles = (nbelow + 15) / 16;
+    typedef typename std::conditional<std::is_same<T, double>::value, d4, f4>::type acc_t;
+    for (int tile = wave; tile < rtiles * (CW / 16); tile += 4) {
+      const int ti = tile / (CW / 16), tj = tile % (CW / 16);
+      const int rbase = rb + ti * 16;       // row offset within the block (relative to r0)
+      acc_t acc;
 #pragma unroll
-      for (int t = 0; t < RB; ++t)
-        if (t < rb) s -= Lb[rr * (RB + 1) + t] * X[(r0 + t) * P + c];
-      X[(r0 + rr) * P + c] = s;
+      for (int v = 0; v < 4; ++v) {
+        const int r = std::is_same<T, double>::value ? (lane / 16 + 4 * v) : (4 * (lane / 16) + v);
+        const int rr = rbase + r;
+        acc[v] = (rr < rows) ? X[(r0 + rr) * PX + tj * 16 + (lane & 15)] : (T)0;
+      }
+#pragma unroll
+      for (int kc = 0; kc < RB / 4; ++kc) {
+        const int ar = rbase + (lane & 15), ak = kc * 4 + lane / 16;
+        const T af = (ar < rows && ak < rb) ? -Lb[ar * PL + ak] : (T)0;
+        const T bf = (ak < rb) ? X[(r0 + ak) * PX + tj * 16 + (lane & 15)] : (T)0;
+        if constexpr (std::is_same<T, double>::value)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, acc, 0, 0, 0);
+        else
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = std::is_same<T, double>::value ? (lane / 16 + 4 * v) : (4 * (lane / 16) + v);
+        const int rr = rbase + r;
+        if (rr < rows) X[(r0 + rr) * PX + tj * 16 + (lane & 15)] = acc[v];
+      }
     }
   }
   __syncthreads();
   for (int idx = tid; idx < jb * cw; idx += 256) {
     const int c = idx / jb, r = idx % jb;
-    Xg[r + (size_t)(c0 + c) * lda] = X[r * P + c];
+    Xg[r + (size_t)(c0 + c) * lda] = X[r * PX + c];
   }
 }
 
@@ -590,16 +614,16 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
     }
     if (ce > cb) {
       const int nc = ce - cb;
-      // 16 columns per workgroup in FP64, 32 in FP32 (two workgroups per CU at jb = 256)
-      int CW = sizeof(T) == 8 ? 16 : 32;
+      // 32 columns per workgroup
+      constexpr int CW = 32;
       size_t sm = ((size_t)jb * (CW + 1) + (size_t)jb * 17) * sizeof(T);
       KScope* kt = new KScope(c.timer, CDS_KC_TRSM, s, batch * (double)jb * jb * nc, 0.0);
       if (jb <= 256)
         hipLaunchKernelGGL((trsm_llnu_kernel<T, 16>), dim3((nc + CW - 1) / CW, batch), dim3(256), sm, s,
-                           (const T*)(A + k + (size_t)k * lda), A + k + (size_t)cb * lda, lda, strideA, jb, nc, CW);
+                           (const T*)(A + k + (size_t)k * lda), A + k + (size_t)cb * lda, lda, strideA, jb, nc);
       else
         hipLaunchKernelGGL((trsm_llnu_kernel<T, 32>), dim3((nc + CW - 1) / CW, batch), dim3(256), sm, s,
-                           (const T*)(A + k + (size_t)k * lda), A + k + (size_t)cb * lda, lda, strideA, jb, nc, CW);
+                           (const T*)(A + k + (size_t)k * lda), A + k + (size_t)cb * lda, lda, strideA, jb, nc);
       delete kt;
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;

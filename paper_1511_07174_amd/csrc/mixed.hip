@@ -132,6 +132,59 @@ __global__ void __launch_bounds__(256) residual_kernel(const double* A0, int64_t
   }
 }
 
+// Residual, op N, split over column chunks: part[chunk][row] = sum over the chunk of A(row, j) x_j.
+// 256 rows per workgroup (one per thread, 2 KB contiguous per column), 8 columns per step.
+__global__ void __launch_bounds__(256) residual_part_kernel(const double* A0, int64_t lda, int64_t strideA,
+                                                            const double* X0, int64_t ldx, int64_t strideX, int n,
+                                                            int c, int chunk, double* part, const int* active) {
+  const int b = blockIdx.z;
+  if (active && active[b] == 0) return;
+  const double* A = A0 + (size_t)b * strideA;
+  const double* x = X0 + (size_t)b * strideX + (size_t)c * ldx;
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int j0 = blockIdx.y * chunk, j1 = min(n, j0 + chunk);
+  double s0 = 0.0, s1 = 0.0;
+  if (r < n) {
+    int j = j0;
+    for (; j + 8 <= j1; j += 8) {
+      double a[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) a[t] = A[r + (size_t)(j + t) * lda];
+#pragma unroll
+      for (int t = 0; t < 8; t += 2) {
+        s0 = fma(a[t], x[j + t], s0);
+        s1 = fma(a[t + 1], x[j + t + 1], s1);
+      }
+    }
+    for (; j < j1; ++j) s0 = fma(A[r + (size_t)j * lda], x[j], s0);
+    part[((size_t)b * gridDim.y + blockIdx.y) * n + r] = s0 + s1;
+  }
+}
+
+// R(:, c) = B(:, c) - sum_chunk part[chunk] (fixed order) and the inf-norms of R(:, c), X(:, c).
+__global__ void __launch_bounds__(256) residual_finish_kernel(const double* X0, int64_t ldx, int64_t strideX,
+                                                              const double* B0, int64_t ldb, int64_t strideB,
+                                                              double* R0, int64_t ldr, int64_t strideR, int n, int c,
+                                                              int nrhs, int nchunk, const double* part,
+                                                              double* rnorm, double* xnorm, const int* active) {
+  const int b = blockIdx.y;
+  if (active && active[b] == 0) return;
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  double rv = 0.0, xv = 0.0;
+  if (r < n) {
+    double s = 0.0;
+    for (int k = 0; k < nchunk; ++k) s += part[((size_t)b * nchunk + k) * n + r];
+    rv = B0[(size_t)b * strideB + (size_t)c * ldb + r] - s;
+    R0[(size_t)b * strideR + (size_t)c * ldr + r] = rv;
+    xv = X0[(size_t)b * strideX + (size_t)c * ldx + r];
+  }
+  double m = wave_max(fabs(rv)), xm = wave_max(fabs(xv));
+  if ((threadIdx.x & 63) == 0) {
+    atomic_max_nonneg(rnorm + (size_t)b * nrhs + c, m);
+    atomic_max_nonneg(xnorm + (size_t)b * nrhs + c, xm);
+  }
+}
+
 // Refinement state per matrix: eta history and the active flag.
 struct IrState {
   double eta_prev, eta_prev2;
@@ -389,11 +442,12 @@ hipError_t launch_outer(int m, int n, int k, double alpha, const double* X, int6
 //   solves (which keeps its own error region view at the same error word).
 // ---------------------------------------------------------------------------------
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr int kResChunks = 16;   // column chunks of the split residual
 
 static size_t ir_small_bytes(int n, int nrhs, int batch) {
   return al256(batch * 8) + 2 * al256((size_t)batch * nrhs * 8) + al256(batch * sizeof(IrState)) +
          al256(batch * 4) + al256(batch * 4 * 2) + al256(batch * 4) + 2 * al256((size_t)batch * n * 4) +
-         al256((size_t)batch * n * nrhs * 8);
+         al256((size_t)batch * n * nrhs * 8) + al256((size_t)batch * kResChunks * n * 8);
 }
 
 size_t ir_ws_bytes(int n, int nrhs, int batch, int nb, int chol, int fallback) {
@@ -410,7 +464,7 @@ size_t ir_ws_bytes(int n, int nrhs, int batch, int nb, int chol, int fallback) {
 
 struct IrWs {
   double* anorm; double* rnorm; double* xnorm; IrState* st; int* active; int* scale; int32_t* info;
-  int32_t* perm; int32_t* gmap; double* R;
+  int32_t* perm; int32_t* gmap; double* R; double* part;
   double* fbA; int32_t* fbpiv; int32_t* fbinfo;
   void* inner; size_t inner_bytes;
 };
@@ -428,6 +482,7 @@ static bool carve(void* ws, size_t ws_bytes, int n, int nrhs, int batch, int fal
   w.perm = (int32_t*)p; p += al256((size_t)batch * n * 4);
   w.gmap = (int32_t*)p; p += al256((size_t)batch * n * 4);
   w.R = (double*)p; p += al256((size_t)batch * n * nrhs * 8);
+  w.part = (double*)p; p += al256((size_t)batch * kResChunks * n * 8);
   if (fallback) {
     w.fbA = (double*)p; p += al256((size_t)batch * n * n * 8);
     w.fbpiv = (int32_t*)p; p += al256((size_t)batch * n * 4);
@@ -469,7 +524,18 @@ static cds_status_t refine(Ctx& c, const IrWs& w, int trans, int chol, int n, in
   for (int it = 0; it <= max_iter; ++it) {
     KScope* ks = new KScope(c.timer, CDS_KC_RESIDUAL, s, 2.0 * batch * n * (double)n * nrhs,
                             8.0 * batch * ((chol ? 0.5 : 1.0) * n * (double)n * nrhs + 3.0 * n * nrhs));
-    if (!chol) {
+    if (!chol && !trans) {
+      const int rb256 = (n + 255) / 256;
+      const int nchunk = std::max(1, std::min(kResChunks, 1024 / std::max(1, rb256 * batch)));
+      const int chunk = (n + nchunk - 1) / nchunk;
+      for (int cc = 0; cc < nrhs; ++cc) {
+        hipLaunchKernelGGL(residual_part_kernel, dim3(rb256, nchunk, batch), dim3(256), 0, s, A, lda, strideA,
+                           (const double*)X, ldx, strideX, n, cc, chunk, w.part, (const int*)w.active);
+        hipLaunchKernelGGL(residual_finish_kernel, dim3(rb256, batch), dim3(256), 0, s, (const double*)X, ldx,
+                           strideX, B, ldb, strideB, w.R, (int64_t)n, (int64_t)n * nrhs, n, cc, nrhs, nchunk,
+                           (const double*)w.part, w.rnorm, w.xnorm, (const int*)w.active);
+      }
+    } else if (!chol) {
       hipLaunchKernelGGL(residual_kernel, dim3(rblocks, batch), dim3(256), 0, s, A, lda, strideA, (const double*)X,
                          ldx, strideX, B, ldb, strideB, w.R, (int64_t)n, (int64_t)n * nrhs, n, nrhs, trans, w.rnorm,
                          w.xnorm, (const int*)w.active);
