@@ -58,11 +58,13 @@ struct SlotLayout {
 // Column-step exchange, executed by wave 0 of every panel workgroup: this
 // workgroup's best candidate (from the per-wave results) is published with its
 // row, then every workgroup's header is read and the global pivot agreed on.
-// lf holds the workgroup's rows of the leaf (row-major, pitch W + 1).
+// rowbuf[w] holds the leaf row of wave w's best candidate, jbuf row j (staged
+// by their owner threads before the barrier that precedes the exchange).
 template <typename T, int W>
-__device__ __forceinline__ void colstep_exchange(uint64_t* slots, const SlotLayout<T, W>& L, int g, int wl, int j,
-                                                 int par, uint32_t flag, const T* red_mag, const int* red_row,
-                                                 const T (*lf)[W + 1], T* prow, T* jrow, int* s_p, int* err) {
+__device__ __forceinline__ void colstep_exchange(uint64_t* slots, const SlotLayout<T, W>& L, int g, int m, int wl,
+                                                 int j, int par, uint32_t flag, const T* red_mag, const int* red_row,
+                                                 const T (*rowbuf)[W], const T* jbuf, T* prow, T* jrow, int* s_p,
+                                                 int* err) {
   constexpr int LLW = LLWords<T>::n;
   const int lane = lane_id();
   T mag = lane < 4 ? red_mag[lane] : (T)-1;
@@ -80,8 +82,9 @@ __device__ __forceinline__ void colstep_exchange(uint64_t* slots, const SlotLayo
     ll_store_val(hdr, mag, flag);
     ll_store(hdr + LLW, (uint32_t)row, flag);
   }
-  if (mag >= (T)0 && lane < wl) ll_store_val(slots + L.cand(par, g) + lane * LLW, lf[row - g * PNT][lane], flag);
-  if (j / PNT == g && lane < wl) ll_store_val(slots + L.rowj(par) + lane * LLW, lf[j - g * PNT][lane], flag);
+  if (mag >= (T)0 && lane < wl)
+    ll_store_val(slots + L.cand(par, g) + lane * LLW, rowbuf[(row - g * PNT) >> 6][lane], flag);
+  if (j / PNT == g && lane < wl) ll_store_val(slots + L.rowj(par) + lane * LLW, jbuf[lane], flag);
   // every workgroup's header (one combined wait per lane)
   T bm = (T)-1;
   int br = 0x7fffffff;
@@ -106,10 +109,13 @@ __device__ __forceinline__ void colstep_exchange(uint64_t* slots, const SlotLayo
     bm = take ? om : bm;
     br = take ? orow : br;
   }
-  const int p = br;
+  // a column without any comparable candidate (NaN entries) keeps row j; the row then comes from
+  // row j's own message, which its owner always publishes
+  const int p = (br >= j && br < m) ? br : j;
   const int gp = p / PNT;
   if (lane < wl) {
-    const uint64_t* ptr[2] = {slots + L.cand(par, gp) + lane * LLW, slots + L.rowj(par) + lane * LLW};
+    const uint64_t* ptr[2] = {slots + (p == j ? L.rowj(par) : L.cand(par, gp)) + lane * LLW,
+                              slots + L.rowj(par) + lane * LLW};
     const bool valid[2] = {true, p != j};
     T v[2];
     ll_wait_vals<T, 2>(ptr, valid, flag, err, v);
@@ -121,9 +127,10 @@ __device__ __forceinline__ void colstep_exchange(uint64_t* slots, const SlotLayo
 
 // Compose the leaf's sequential interchanges (c0+cc <-> piv[cc]) into a list of
 // (dst, src) moves.  Entries 0..wl-1 are the top positions c0..c0+wl-1 (src may
-// equal dst); later entries are the other moved positions.  Wave 0 only.
+// equal dst); later entries are the other moved positions.  Wave 0 only; returns
+// the entry count in every lane.
 template <int W>
-__device__ void compose_leaf(const int* s_piv, int c0, int wl, int* s_dst, int* s_src, int* s_ne) {
+__device__ int compose_leaf(const int* s_piv, int c0, int wl, int* s_dst, int* s_src, int* s_ne) {
   const int lane = lane_id();
   int mypos = -1, mysrc = -1, cnt = 0;   // lane L holds table entry L (2W <= 64)
   for (int cc = 0; cc < wl; ++cc) {
@@ -159,12 +166,48 @@ __device__ void compose_leaf(const int* s_piv, int c0, int wl, int* s_dst, int* 
     s_dst[idx] = mypos;
     s_src[idx] = mysrc;
   }
-  if (lane == 0) *s_ne = wl + __popcll(mo);
+  const int ne = wl + __popcll(mo);
+  if (lane == 0) *s_ne = ne;
+  return ne;
 }
 
+// Compact the entries of a leaf's move list whose source (src_side) or
+// destination row lies in this workgroup's rows.  Wave 0 only; ne <= 3W <= 128.
+__device__ void compact_entries(const int* s_dst, const int* s_src, int ne, int g, int* s_own, int* s_nown,
+                                int* s_dl, int* s_ndl) {
+  const int lane = lane_id();
+  int no = 0, nd = 0;
+  for (int e0 = 0; e0 < ne; e0 += kWave) {
+    const int e = e0 + lane;
+    const bool in = e < ne;
+    const bool so = in && s_src[e] / PNT == g;
+    const bool dO = in && s_dst[e] / PNT == g && s_dst[e] != s_src[e];
+    const uint64_t mo = __ballot(so), md = __ballot(dO);
+    const uint64_t below = (1ull << lane) - 1ull;
+    if (so) s_own[no + __popcll(mo & below)] = e;
+    if (dO) s_dl[nd + __popcll(md & below)] = e;
+    no += __popcll(mo);
+    nd += __popcll(md);
+  }
+  if (lane == 0) {
+    *s_nown = no;
+    *s_ndl = nd;
+  }
+}
+
+// The panel: G workgroups of PNT rows.  Per leaf of W columns, each thread
+// keeps its row of the leaf in registers through the column loop; after the
+// leaf, the leaf's interchanges move rows between workgroups in one
+// publish/consume round of flag+payload words, every workgroup forms
+// U_right = L11^{-1} P_top for the right part of the panel, and updates its own
+// rows with an MFMA product; the first W updated columns (the next leaf) stay in
+// LDS.
 template <typename T, int W>
 __global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
   constexpr int LLW = LLWords<T>::n;
+  constexpr bool F64 = std::is_same<T, double>::value;
+  typedef typename std::conditional<F64, d4, f4>::type acc_t;
+  static_assert(W == 32, "the MFMA update assumes 32-column leaves");
   const int g = blockIdx.x, b = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m = P.n - P.k, jb = P.jb;
@@ -178,7 +221,9 @@ __global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
   const int row = g * PNT + tid;
   const bool own = row < m;
 
-  __shared__ T lf[PNT][W + 1];      // this workgroup's rows of the current leaf
+  __shared__ T lf[PNT][W + 1];      // this workgroup's rows of the leaf (the MFMA B operand, the next leaf)
+  __shared__ T rowbuf[4][W];        // per-wave best candidate row
+  __shared__ T jbuf[W];             // row j (owner workgroup)
   __shared__ T red_mag[4];
   __shared__ int red_row[4];
   __shared__ T prow[W];
@@ -187,189 +232,266 @@ __global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
   __shared__ T L11[W][W + 1];
   __shared__ int s_piv[W];
   __shared__ int s_dst[3 * W], s_src[3 * W];
-  __shared__ int s_ne;
-  __shared__ T Ubuf[W][PCH + 16];
+  __shared__ int s_own[3 * W], s_dl[3 * W];
+  __shared__ int s_ne, s_nown, s_ndl;
+  __shared__ T Ubuf[W][PCH + 8];
 
   int leafc = 0;
   for (int c0 = 0; c0 < jb; c0 += W, ++leafc) {
     const int wl = min(W, jb - c0);
+    const int c1 = c0 + wl;
     const bool act = own && row >= c0;
-    {
-      T v[W];
+    T v[W];
+    if (c0 == 0) {
 #pragma unroll
-      for (int cc = 0; cc < W; ++cc) v[cc] = (act && cc < wl) ? A[row + (size_t)(c0 + cc) * lda] : (T)0;
+      for (int cc = 0; cc < W; ++cc) v[cc] = (act && cc < wl) ? A[row + (size_t)cc * lda] : (T)0;
+    } else {
+      // written by this thread's own wave at the end of the previous leaf
 #pragma unroll
-      for (int cc = 0; cc < W; ++cc) lf[tid][cc] = v[cc];
+      for (int cc = 0; cc < W; ++cc) v[cc] = (act && cc < wl) ? lf[tid][cc] : (T)0;
     }
     for (int cc = 0; cc < wl; ++cc) {
       const int j = c0 + cc;
       const int par = j & 1;
       const uint32_t flag = (uint32_t)(P.k + j + 1);
+      T x = v[0];
+#pragma unroll
+      for (int c2 = 1; c2 < W; ++c2)
+        if (c2 == cc) x = v[c2];
       const bool cand_ok = own && row >= j;
-      T mag = cand_ok ? fabs(lf[tid][cc]) : (T)-1;
+      T mag = cand_ok ? fabs(x) : (T)-1;
       int r = cand_ok ? row : 0x7fffffff;
       wave_argmax(mag, r);
+      if (cand_ok && row == r) {
+#pragma unroll
+        for (int c2 = 0; c2 < W; ++c2) rowbuf[wave][c2] = v[c2];
+      }
+      if (own && row == j) {
+#pragma unroll
+        for (int c2 = 0; c2 < W; ++c2) jbuf[c2] = v[c2];
+      }
       if (lane == 0) { red_mag[wave] = mag; red_row[wave] = r; }
       __syncthreads();
       if (wave == 0)
-        colstep_exchange<T, W>(slots, L, g, wl, j, par, flag, red_mag, red_row, lf, prow, jrow, &s_p, P.err);
+        colstep_exchange<T, W>(slots, L, g, m, wl, j, par, flag, red_mag, red_row, rowbuf, jbuf, prow, jrow, &s_p,
+                               P.err);
       __syncthreads();
       const int p = s_p;
       T pr[W];
 #pragma unroll
       for (int c2 = 0; c2 < W; ++c2) pr[c2] = prow[c2];
       const T piv = prow[cc];
-      if (own && (row == j || row == p)) {
-        // interchange: row j takes the pivot row, row p the old row j
+      if (own && row == j) {
 #pragma unroll
         for (int c2 = 0; c2 < W; ++c2)
-          if (c2 < wl) lf[tid][c2] = (row == j) ? pr[c2] : jrow[c2];
+          if (c2 < wl) v[c2] = pr[c2];
+      } else if (own && row == p) {
+#pragma unroll
+        for (int c2 = 0; c2 < W; ++c2)
+          if (c2 < wl) v[c2] = jrow[c2];
+        x = jrow[cc];
       }
       if (own && row > j && piv != (T)0) {
-        const T lmul = lf[tid][cc] / piv;
+        const T lmul = x / piv;
 #pragma unroll
-        for (int c2 = 0; c2 < W; ++c2)
-          if (c2 > cc && c2 < wl) lf[tid][c2] = lf[tid][c2] - lmul * pr[c2];
-        lf[tid][cc] = lmul;
+        for (int c2 = 0; c2 < W; ++c2) {
+          const T upd = v[c2] - lmul * pr[c2];
+          v[c2] = (c2 > cc && c2 < wl) ? upd : (c2 == cc ? lmul : v[c2]);
+        }
       }
       if (tid < W) L11[cc][tid] = prow[tid];
       if (tid == 0) {
         s_piv[cc] = p;
-        // a zero pivot is recorded at once (rare); ipiv is written once per leaf so that no
-        // global store is outstanding at the next barrier
+        // a zero pivot is recorded at once (rare); ipiv is written once per leaf
         if (g == 0 && piv == (T)0) atomicCAS(P.info + b, 0, P.k + j + 1);
       }
     }
-    // write back the leaf columns
+    // the leaf's final values (up to later interchanges) and the MFMA operand copy
     if (act) {
-      for (int cc = 0; cc < wl; ++cc) A[row + (size_t)(c0 + cc) * lda] = lf[tid][cc];
+#pragma unroll
+      for (int cc = 0; cc < W; ++cc)
+        if (cc < wl) A[row + (size_t)(c0 + cc) * lda] = v[cc];
     }
+#pragma unroll
+    for (int cc = 0; cc < W; ++cc) lf[tid][cc] = v[cc];
     __syncthreads();
-    if (wave == 0) compose_leaf<W>(s_piv, c0, wl, s_dst, s_src, &s_ne);
+    if (wave == 0) {
+      const int ne0 = compose_leaf<W>(s_piv, c0, wl, s_dst, s_src, &s_ne);
+      // the lists written by other lanes of this wave are read below: order the LDS accesses
+      wave_fence();
+      compact_entries(s_dst, s_src, ne0, g, s_own, &s_nown, s_dl, &s_ndl);
+    }
     __syncthreads();
     if (g == 0 && tid < wl) ipiv[c0 + tid] = P.k + s_piv[tid] + 1;
     const int ne = s_ne;
     const int spar = leafc & 1;
     const uint32_t sflag = (uint32_t)(P.k + c0 + 1);
-    const int nv = jb - wl;   // non-leaf columns of the panel
+    const int nv = jb - wl;   // non-leaf columns of the panel: [0, c0) and [c1, jb)
     if (g == 0) {
       for (int e = tid; e < ne; e += PNT) pairs[leafc * 3 * W + e] = make_int2(s_dst[e] + P.k, s_src[e] + P.k);
       if (tid == 0) pair_cnt[leafc] = ne;
     }
-    if (nv > 0) {
-      // publish the rows this workgroup is the source of (columns outside the leaf); items
-      // (entry, column) are flattened and handled in batches so that the loads overlap
-      {
-        constexpr int SB8 = 8;
-        const int total = ne * nv;
-        for (int base = 0; base < total; base += PNT * SB8) {
-          T v[SB8];
-          int64_t off[SB8];
-          bool ok[SB8];
+    if (nv == 0) continue;
+    constexpr int SB = 16;
+    // publish the non-leaf columns of the rows this workgroup is the source of
+    {
+      const int nown = s_nown;
+      const int total = nown * nv;
+      for (int base = 0; base < total; base += PNT * SB) {
+        T vv[SB];
+        int64_t off[SB];
+        bool ok[SB];
 #pragma unroll
-          for (int q = 0; q < SB8; ++q) {
-            const int it = base + q * PNT + tid;
-            const int e = it / max(nv, 1), idx = it - e * nv;
-            ok[q] = it < total && (s_src[min(e, ne - 1)] / PNT == g);
+        for (int q = 0; q < SB; ++q) {
+          const int it = base + q * PNT + tid;
+          ok[q] = it < total;
+          off[q] = 0;
+          vv[q] = (T)0;
+          if (ok[q]) {
+            const int ei = it / nv, idx = it - ei * nv;
+            const int e = s_own[ei];
             const int col = idx < c0 ? idx : idx + wl;
-            off[q] = ok[q] ? (int64_t)L.sw(spar, e) + (int64_t)idx * LLW : 0;
-            v[q] = ok[q] ? A[s_src[e] + (size_t)col * lda] : (T)0;
-          }
-#pragma unroll
-          for (int q = 0; q < SB8; ++q)
-            if (ok[q]) ll_store_val(slots + off[q], v[q], sflag);
-        }
-      }
-      __syncthreads();
-      // move rows into the destinations this workgroup owns
-      {
-        constexpr int SB8 = 8;
-        const int total = ne * nv;
-        for (int base = 0; base < total; base += PNT * SB8) {
-          const uint64_t* ptr[SB8];
-          bool ok[SB8];
-          size_t dsto[SB8];
-          T v[SB8];
-#pragma unroll
-          for (int q = 0; q < SB8; ++q) {
-            const int it = base + q * PNT + tid;
-            const int e = it / max(nv, 1), idx = it - e * nv;
-            const int ec = min(e, ne - 1);
-            ok[q] = it < total && (s_dst[ec] / PNT == g) && s_dst[ec] != s_src[ec];
-            const int col = idx < c0 ? idx : idx + wl;
-            ptr[q] = slots + L.sw(spar, ec) + (int64_t)idx * LLW;
-            dsto[q] = ok[q] ? (size_t)s_dst[ec] + (size_t)col * lda : 0;
-          }
-          ll_wait_vals<T, SB8>(ptr, ok, sflag, P.err, v);
-#pragma unroll
-          for (int q = 0; q < SB8; ++q)
-            if (ok[q]) A[dsto[q]] = v[q];
-        }
-      }
-      __syncthreads();
-      // U_right = L11^{-1} P_top and the update of the rows below, chunk by chunk
-      const int c1 = c0 + wl;
-      for (int x0 = c1; x0 < jb; x0 += PCH) {
-        const int cw = min(PCH, jb - x0);
-        const int total = wl * cw;
-        for (int base = 0; base < total; base += PNT * 8) {
-          const uint64_t* ptr[8];
-          bool valid[8];
-          T v[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const int idx = base + q * PNT + tid;
-            valid[q] = idx < total;
-            const int cc = valid[q] ? idx / cw : 0, x = valid[q] ? idx % cw : 0;
-            ptr[q] = slots + L.sw(spar, cc) + (int64_t)(x0 + x - wl) * LLW;
-          }
-          ll_wait_vals<T, 8>(ptr, valid, sflag, P.err, v);
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const int idx = base + q * PNT + tid;
-            if (valid[q]) Ubuf[idx / cw][idx % cw] = v[q];
+            off[q] = (int64_t)L.sw(spar, e) + (int64_t)idx * LLW;
+            vv[q] = A[s_src[e] + (size_t)col * lda];
           }
         }
-        __syncthreads();
-        if (tid < cw) {
-          for (int i = 1; i < wl; ++i) {
-            T s = Ubuf[i][tid];
-            for (int t = 0; t < i; ++t) s -= L11[i][t] * Ubuf[t][tid];
-            Ubuf[i][tid] = s;
-          }
-        }
-        __syncthreads();
-        for (int idx = tid; idx < wl * cw; idx += PNT) {
-          const int cc = idx / cw, x = idx % cw;
-          const int r = c0 + cc;
-          if (r / PNT == g) A[r + (size_t)(x0 + x) * lda] = Ubuf[cc][x];
-        }
-        if (own && row >= c1) {
-          // batches of GX columns, the loads of the next batch in flight during this one
-          constexpr int GX = 8;
-          T cur[GX], nxt[GX];
 #pragma unroll
-          for (int q = 0; q < GX; ++q) cur[q] = (q < cw) ? A[row + (size_t)(x0 + q) * lda] : (T)0;
-          for (int x = 0; x < cw; x += GX) {
-#pragma unroll
-            for (int q = 0; q < GX; ++q)
-              nxt[q] = (x + GX + q < cw) ? A[row + (size_t)(x0 + x + GX + q) * lda] : (T)0;
-            for (int cc = 0; cc < wl; ++cc) {
-              const T lc = lf[tid][cc];
-#pragma unroll
-              for (int q = 0; q < GX; ++q) cur[q] -= lc * Ubuf[cc][x + q];
-            }
-#pragma unroll
-            for (int q = 0; q < GX; ++q)
-              if (x + q < cw) A[row + (size_t)(x0 + x + q) * lda] = cur[q];
-#pragma unroll
-            for (int q = 0; q < GX; ++q) cur[q] = nxt[q];
-          }
-        }
-        __syncthreads();
+        for (int q = 0; q < SB; ++q)
+          if (ok[q]) ll_store_val(slots + off[q], vv[q], sflag);
       }
     }
-    __syncthreads();
+    __syncthreads();   // every read of a source row of this workgroup precedes the writes below
+    const int ndl = s_ndl;
+    // the MFMA B operand (L21 of this wave's rows), read before the next leaf overwrites lf
+    const int wr = wave * 64;                      // first row of this wave within the workgroup
+    T bop[4][W / 4];
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int kc = 0; kc < W / 4; ++kc) bop[rt][kc] = lf[wr + rt * 16 + (lane & 15)][4 * kc + (lane >> 4)];
+    bool first = true;
+    // the first pass also takes the rows this workgroup receives, so it runs for the last leaf too
+    for (int x0 = c1; x0 < jb || first; x0 += PCH, first = false) {
+      const int cw = max(0, min(PCH, jb - x0));
+      // one combined wait: P_top's columns [x0, x0 + cw) into Ubuf and (first chunk) the rows this
+      // workgroup receives (top destinations take only the left part; U_right overwrites the rest)
+      {
+        const int nU = wl * cw;
+        const int total = nU + (first ? ndl * nv : 0);
+        for (int base = 0; base < total; base += PNT * SB) {
+          const uint64_t* ptr[SB];
+          bool ok[SB];
+          int64_t dsto[SB];
+          T vv[SB];
+#pragma unroll
+          for (int q = 0; q < SB; ++q) {
+            const int it = base + q * PNT + tid;
+            ok[q] = it < total;
+            if (it < nU) {
+              const int cc = it / cw, x = it - cc * cw;
+              ptr[q] = slots + L.sw(spar, cc) + (int64_t)(x0 + x - wl) * LLW;
+              dsto[q] = -1 - (int64_t)(cc * (PCH + 8) + x);
+            } else if (ok[q]) {
+              const int it2 = it - nU;
+              const int ei = it2 / nv, idx = it2 - ei * nv;
+              const int e = s_dl[ei];
+              const int col = idx < c0 ? idx : idx + wl;
+              ok[q] = e >= wl || idx < c0;
+              ptr[q] = slots + L.sw(spar, e) + (int64_t)idx * LLW;
+              dsto[q] = (int64_t)s_dst[e] + (int64_t)col * lda;
+            } else {
+              ptr[q] = slots;
+              dsto[q] = 0;
+            }
+          }
+          ll_wait_vals<T, SB>(ptr, ok, sflag, P.err, vv);
+#pragma unroll
+          for (int q = 0; q < SB; ++q) {
+            if (!ok[q]) continue;
+            if (dsto[q] < 0) (&Ubuf[0][0])[-1 - dsto[q]] = vv[q];
+            else A[dsto[q]] = vv[q];
+          }
+        }
+      }
+      __syncthreads();
+      if (cw == 0) break;
+      // U_right = L11^{-1} P_top, one thread per column
+      if (tid < cw) {
+        T u[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) u[i] = (i < wl) ? Ubuf[i][tid] : (T)0;
+#pragma unroll
+        for (int i = 1; i < W; ++i) {
+          T acc = u[i];
+#pragma unroll
+          for (int t = 0; t < i; ++t) acc -= L11[i][t] * u[t];
+          u[i] = (i < wl) ? acc : (T)0;
+        }
+#pragma unroll
+        for (int i = 0; i < W; ++i) Ubuf[i][tid] = u[i];
+      }
+      __syncthreads();
+      // the top rows take U_right
+      for (int idx = tid; idx < wl * cw; idx += PNT) {
+        const int cc = idx / cw, x = idx - cc * cw;
+        const int r = c0 + cc;
+        if (r / PNT == g) A[r + (size_t)(x0 + x) * lda] = Ubuf[cc][x];
+      }
+      // rows >= c1 of this wave: C[rows, cols] -= L21[rows, :] U_right[:, cols] on 16x16x4 MFMA tiles,
+      // computed transposed (D = -U^T L21^T) so that a lane's accumulators run down a column.
+      // Sub-chunks of 32 columns; the one holding the next leaf goes last and into lf.
+      {
+        const int nsub = (cw + 31) / 32;
+        for (int si = 0; si < nsub; ++si) {
+          const int sub = first ? (si + 1) % nsub : si;   // the next leaf's columns last
+          const bool to_lds = first && sub == 0;
+          const int xs = x0 + sub * 32;
+          const int cws = min(32, x0 + cw - xs);
+          acc_t acc[2][4];
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+              for (int vq = 0; vq < 4; ++vq) {
+                const int ci = ct * 16 + (F64 ? ((lane >> 4) + 4 * vq) : (4 * (lane >> 4) + vq));
+                const int rr = g * PNT + wr + rt * 16 + (lane & 15);
+                const bool ok = rr < m && rr >= c1 && ci < cws;
+                acc[ct][rt][vq] = ok ? A[rr + (size_t)(xs + ci) * lda] : (T)0;
+              }
+#pragma unroll
+          for (int kc = 0; kc < W / 4; ++kc) {
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct) {
+              const T aop = -Ubuf[4 * kc + (lane >> 4)][xs - x0 + ct * 16 + (lane & 15)];
+#pragma unroll
+              for (int rt = 0; rt < 4; ++rt) {
+                if constexpr (F64)
+                  acc[ct][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop[rt][kc], acc[ct][rt], 0, 0, 0);
+                else
+                  acc[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop[rt][kc], acc[ct][rt], 0, 0, 0);
+              }
+            }
+          }
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+              for (int vq = 0; vq < 4; ++vq) {
+                const int ci = ct * 16 + (F64 ? ((lane >> 4) + 4 * vq) : (4 * (lane >> 4) + vq));
+                const int rl = wr + rt * 16 + (lane & 15);
+                const int rr = g * PNT + rl;
+                if (to_lds) {
+                  lf[rl][ci] = acc[ct][rt][vq];
+                } else if (rr < m && rr >= c1 && ci < cws) {
+                  A[rr + (size_t)(xs + ci) * lda] = acc[ct][rt][vq];
+                }
+              }
+        }
+      }
+      __syncthreads();   // Ubuf is reloaded by the next chunk
+    }
   }
 }
 
