@@ -250,6 +250,54 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Wave-uniform max / min of a 32-bit value: DPP exchanges inside each 16-lane
+// row (quad permutes, half-row and row mirrors), then the four row results
+// through readlane.  Every lane of the wave must be active.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
+  const uint32_t a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+  const uint32_t c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+  return max(max(a, b), max(c, d));
+}
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false));
+  const uint32_t a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+  const uint32_t c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+  return min(min(a, b), min(c, d));
+}
+
+// Pivot search over the wave: the largest magnitude wins, ties go to the lowest
+// row.  Lanes with valid = false, a NaN or a negative magnitude take no part.
+// Magnitudes are compared through their bit patterns (monotone for values
+// >= 0): the high word first, then the low word among the leaders.  The result
+// is uniform; with no valid lane best_mag = -1 and best_row = INT_MAX.
+template <typename T>
+__device__ __forceinline__ void wave_pivot_search(T mag, int row, bool valid, T& best_mag, int& best_row) {
+  valid = valid && (mag >= (T)0);   // false for NaN
+  bool lead;
+  if constexpr (sizeof(T) == 8) {
+    const uint64_t bits = (uint64_t)__double_as_longlong(mag);
+    const uint32_t hi = valid ? (uint32_t)(bits >> 32) + 1u : 0u;
+    const uint32_t mh = wave_max_u32(hi);
+    const uint32_t lo = (valid && hi == mh) ? (uint32_t)bits : 0u;
+    const uint32_t ml = wave_max_u32(lo);
+    lead = valid && hi == mh && (uint32_t)bits == ml;
+    best_mag = mh == 0u ? (T)-1 : __longlong_as_double((long long)(((uint64_t)(mh - 1u) << 32) | ml));
+  } else {
+    const uint32_t k = valid ? __float_as_uint(mag) + 1u : 0u;
+    const uint32_t mk = wave_max_u32(k);
+    lead = valid && k == mk;
+    best_mag = mk == 0u ? (T)-1 : __uint_as_float(mk - 1u);
+  }
+  best_row = (int)wave_min_u32(lead ? (uint32_t)row : 0x7fffffffu);
+}
+
 __device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // Orders LDS accesses between the lanes of one wave (lanes run in lockstep and

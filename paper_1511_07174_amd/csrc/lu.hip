@@ -60,22 +60,25 @@ struct SlotLayout {
 // row, then every workgroup's header is read and the global pivot agreed on.
 // rowbuf[w] holds the leaf row of wave w's best candidate, jbuf row j (staged
 // by their owner threads before the barrier that precedes the exchange).
+// Outputs: prow = the pivot row (zero beyond wl), prm = prow restricted to the
+// columns the elimination updates (cc < c < wl), jrow = row j, *s_p = pivot row.
 template <typename T, int W>
 __device__ __forceinline__ void colstep_exchange(uint64_t* slots, const SlotLayout<T, W>& L, int g, int m, int wl,
-                                                 int j, int par, uint32_t flag, const T* red_mag, const int* red_row,
-                                                 const T (*rowbuf)[W], const T* jbuf, T* prow, T* jrow, int* s_p,
-                                                 int* err) {
+                                                 int cc, int j, int par, uint32_t flag, const T* red_mag,
+                                                 const int* red_row, const T (*rowbuf)[W], const T* jbuf, T* prow,
+                                                 T* prm, T* jrow, int* s_p, int* err) {
   constexpr int LLW = LLWords<T>::n;
   const int lane = lane_id();
-  T mag = lane < 4 ? red_mag[lane] : (T)-1;
-  int row = lane < 4 ? red_row[lane] : 0x7fffffff;
+  T mag = red_mag[0];
+  int row = red_row[0];
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    T om = shfl_xor(mag, m);
-    int orow = shfl_xor(row, m);
-    bool take = (om > mag) || (om == mag && orow < row);
-    mag = take ? om : mag;
-    row = take ? orow : row;
+  for (int w = 1; w < 4; ++w) {
+    const T om = red_mag[w];
+    const int orow = red_row[w];
+    if (om > mag || (om == mag && orow < row)) {
+      mag = om;
+      row = orow;
+    }
   }
   uint64_t* hdr = slots + L.hdr(par, g);
   if (lane == 0) {
@@ -85,7 +88,7 @@ __device__ __forceinline__ void colstep_exchange(uint64_t* slots, const SlotLayo
   if (mag >= (T)0 && lane < wl)
     ll_store_val(slots + L.cand(par, g) + lane * LLW, rowbuf[(row - g * PNT) >> 6][lane], flag);
   if (j / PNT == g && lane < wl) ll_store_val(slots + L.rowj(par) + lane * LLW, jbuf[lane], flag);
-  // every workgroup's header (one combined wait per lane)
+  // every workgroup's header (one combined wait per header)
   T bm = (T)-1;
   int br = 0x7fffffff;
   for (int i = lane; i < L.G; i += kWave) {
@@ -97,29 +100,28 @@ __device__ __forceinline__ void colstep_exchange(uint64_t* slots, const SlotLayo
     else
       mi = __uint_as_float(wv3[0]);
     const int ri = (int)wv3[LLW];
-    bool take = (mi > bm) || (mi == bm && ri < br);
-    bm = take ? mi : bm;
-    br = take ? ri : br;
+    if (mi > bm || (mi == bm && ri < br)) {
+      bm = mi;
+      br = ri;
+    }
   }
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    T om = shfl_xor(bm, m);
-    int orow = shfl_xor(br, m);
-    bool take = (om > bm) || (om == bm && orow < br);
-    bm = take ? om : bm;
-    br = take ? orow : br;
-  }
+  T gm;
+  int gr;
+  wave_pivot_search<T>(bm, br, true, gm, gr);
   // a column without any comparable candidate (NaN entries) keeps row j; the row then comes from
   // row j's own message, which its owner always publishes
-  const int p = (br >= j && br < m) ? br : j;
+  const int p = (gr >= j && gr < m) ? gr : j;
   const int gp = p / PNT;
-  if (lane < wl) {
-    const uint64_t* ptr[2] = {slots + (p == j ? L.rowj(par) : L.cand(par, gp)) + lane * LLW,
-                              slots + L.rowj(par) + lane * LLW};
-    const bool valid[2] = {true, p != j};
-    T v[2];
-    ll_wait_vals<T, 2>(ptr, valid, flag, err, v);
+  if (lane < W) {
+    T v[2] = {(T)0, (T)0};
+    if (lane < wl) {
+      const uint64_t* ptr[2] = {slots + (p == j ? L.rowj(par) : L.cand(par, gp)) + lane * LLW,
+                                slots + L.rowj(par) + lane * LLW};
+      const bool valid[2] = {true, p != j};
+      ll_wait_vals<T, 2>(ptr, valid, flag, err, v);
+    }
     prow[lane] = v[0];
+    prm[lane] = lane > cc ? v[0] : (T)0;
     if (p != j) jrow[lane] = v[1];
   }
   if (lane == 0) *s_p = p;
@@ -227,6 +229,7 @@ __global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
   __shared__ T red_mag[4];
   __shared__ int red_row[4];
   __shared__ T prow[W];
+  __shared__ T prm[W];
   __shared__ T jrow[W];
   __shared__ int s_p;
   __shared__ T L11[W][W + 1];
@@ -254,15 +257,14 @@ __global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
       const int j = c0 + cc;
       const int par = j & 1;
       const uint32_t flag = (uint32_t)(P.k + j + 1);
+      // v[cc] through selects (a dynamic register index would put v in scratch memory)
       T x = v[0];
 #pragma unroll
-      for (int c2 = 1; c2 < W; ++c2)
-        if (c2 == cc) x = v[c2];
-      const bool cand_ok = own && row >= j;
-      T mag = cand_ok ? fabs(x) : (T)-1;
-      int r = cand_ok ? row : 0x7fffffff;
-      wave_argmax(mag, r);
-      if (cand_ok && row == r) {
+      for (int c2 = 1; c2 < W; ++c2) x = (c2 == cc) ? v[c2] : x;
+      T wbm;
+      int wbr;
+      wave_pivot_search<T>(fabs(x), row, own && row >= j, wbm, wbr);
+      if (row == wbr) {
 #pragma unroll
         for (int c2 = 0; c2 < W; ++c2) rowbuf[wave][c2] = v[c2];
       }
@@ -270,34 +272,27 @@ __global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
 #pragma unroll
         for (int c2 = 0; c2 < W; ++c2) jbuf[c2] = v[c2];
       }
-      if (lane == 0) { red_mag[wave] = mag; red_row[wave] = r; }
+      if (lane == 0) { red_mag[wave] = wbm; red_row[wave] = wbr; }
       __syncthreads();
       if (wave == 0)
-        colstep_exchange<T, W>(slots, L, g, m, wl, j, par, flag, red_mag, red_row, rowbuf, jbuf, prow, jrow, &s_p,
-                               P.err);
+        colstep_exchange<T, W>(slots, L, g, m, wl, cc, j, par, flag, red_mag, red_row, rowbuf, jbuf, prow, prm, jrow,
+                               &s_p, P.err);
       __syncthreads();
       const int p = s_p;
-      T pr[W];
-#pragma unroll
-      for (int c2 = 0; c2 < W; ++c2) pr[c2] = prow[c2];
       const T piv = prow[cc];
       if (own && row == j) {
 #pragma unroll
-        for (int c2 = 0; c2 < W; ++c2)
-          if (c2 < wl) v[c2] = pr[c2];
+        for (int c2 = 0; c2 < W; ++c2) v[c2] = prow[c2];
       } else if (own && row == p) {
 #pragma unroll
-        for (int c2 = 0; c2 < W; ++c2)
-          if (c2 < wl) v[c2] = jrow[c2];
+        for (int c2 = 0; c2 < W; ++c2) v[c2] = jrow[c2];
         x = jrow[cc];
       }
       if (own && row > j && piv != (T)0) {
+        // prm is zero outside (cc, wl): one unconditional fused update per column
         const T lmul = x / piv;
 #pragma unroll
-        for (int c2 = 0; c2 < W; ++c2) {
-          const T upd = v[c2] - lmul * pr[c2];
-          v[c2] = (c2 > cc && c2 < wl) ? upd : (c2 == cc ? lmul : v[c2]);
-        }
+        for (int c2 = 0; c2 < W; ++c2) v[c2] = (c2 == cc) ? lmul : fma(-lmul, prm[c2], v[c2]);
       }
       if (tid < W) L11[cc][tid] = prow[tid];
       if (tid == 0) {
