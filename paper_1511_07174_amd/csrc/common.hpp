@@ -298,6 +298,19 @@ __device__ __forceinline__ void wave_pivot_search(T mag, int row, bool valid, T&
   best_row = (int)wave_min_u32(lead ? (uint32_t)row : 0x7fffffffu);
 }
 
+// Value of lane t (wave-uniform t) in every lane, through readlane (no LDS).
+template <typename T>
+__device__ __forceinline__ T lane_bcast(T v, int t) {
+  if constexpr (sizeof(T) == 8) {
+    const long long bits = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)bits, t);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(bits >> 32), t);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+  } else {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), t));
+  }
+}
+
 __device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // Orders LDS accesses between the lanes of one wave (lanes run in lockstep and

@@ -1,7 +1,8 @@
 // Triangular solves of the direct method (Sec. 2, step 2: Ly = b, Ux = y, by
 // forward and back substitution), and the row interchanges of P b.
 //
-//   perm_kernel        ipiv (sequential interchanges) -> row order perm, in LDS.
+//   perm_kernel        ipiv (sequential interchanges) -> row order perm, every
+//                      position traced backwards in parallel.
 //   gather / scatter   Y = B[perm] (op N) or X[perm] = W (op T), with type
 //                      conversion so that the refinement loop can solve in FP32
 //                      for an FP64 residual and add the correction in FP64.
@@ -26,36 +27,46 @@ namespace {
 constexpr int BS = 64;      // rows per block
 constexpr int TNT = 256;    // threads per workgroup
 
-// ipiv -> perm: perm[i] = original row found at position i after all
-// interchanges.  One workgroup per matrix; the map lives in LDS when it fits.
-__global__ void __launch_bounds__(1024) perm_kernel(const int32_t* ipiv0, int64_t strideP, int n, int32_t* perm0,
-                                                    int64_t strideQ, int32_t* gmap0, int use_lds) {
-  extern __shared__ int smap[];
-  const int b = blockIdx.x;
+// ipiv -> perm: perm[i] = original row found at position i after all the
+// interchanges (k <-> ipiv[k] - 1, k = 0, 1, ...).  Each thread traces its
+// position backwards through the interchanges: position cur after interchange
+// k held, before it, the row at k when cur = ipiv[k] - 1, at ipiv[k] - 1 when
+// cur = k, else the row at cur.  Since ipiv[k] - 1 >= k, interchanges above a
+// workgroup's last position never touch its rows and are skipped.  ipiv is
+// staged in LDS in chunks read by every lane at once (a broadcast).
+// Interchange entries out of range are ignored.
+constexpr int PERM_CH = 4096;
+__global__ void __launch_bounds__(256) perm_kernel(const int32_t* ipiv0, int64_t strideP, int n, int32_t* perm0,
+                                                   int64_t strideQ) {
+  __shared__ int sp[PERM_CH];
+  const int b = blockIdx.y;
   const int32_t* ipiv = ipiv0 + (size_t)b * strideP;
   int32_t* perm = perm0 + (size_t)b * strideQ;
-  int* map = use_lds ? smap : (gmap0 + (size_t)b * n);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) map[i] = i;
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    const int lane = threadIdx.x;
-    for (int c0 = 0; c0 < n; c0 += 64) {
-      const int pv = (c0 + lane < n) ? ipiv[c0 + lane] - 1 : c0 + lane;
-      const int cnt = min(64, n - c0);
-      for (int t = 0; t < cnt; ++t) {
-        const int p = __shfl(pv, t);
-        const int s = c0 + t;
-        if (p > s && p < n && lane == 0) {   // valid interchanges only (p >= s by construction)
-          int x = map[s];
-          int y = map[p];
-          map[s] = y;
-          map[p] = x;
-        }
-      }
+  const int i0 = blockIdx.x * 256;
+  int cur = i0 + (int)threadIdx.x;
+  const int kmax = min(n, i0 + 256) - 1;
+  for (int khi = kmax; khi >= 0; khi -= PERM_CH) {
+    const int klo = max(0, khi - PERM_CH + 1);
+    __syncthreads();
+    for (int k = klo + (int)threadIdx.x; k <= khi; k += 256) {
+      const int pv = ipiv[k] - 1;
+      sp[k - klo] = (pv > k && pv < n) ? pv : k;   // an invalid entry becomes k <-> k
+    }
+    __syncthreads();
+    int k = khi;
+    for (; k - 7 >= klo; k -= 8) {
+      int pv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) pv[u] = sp[k - u - klo];   // issued together, off the chain
+#pragma unroll
+      for (int u = 0; u < 8; ++u) cur = (cur == k - u) ? pv[u] : ((cur == pv[u]) ? k - u : cur);
+    }
+    for (; k >= klo; --k) {
+      const int pv = sp[k - klo];
+      cur = (cur == k) ? pv : ((cur == pv) ? k : cur);
     }
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) perm[i] = map[i];
+  if (i0 + (int)threadIdx.x < n) perm[i0 + threadIdx.x] = cur;
 }
 
 // Y[i, c] = (T) B[src(i), c] with src = perm[i] (gather = 1) or identity; skipped when active[b] == 0
@@ -232,6 +243,11 @@ __global__ void __launch_bounds__(TNT) trsv_kernel(TrsvArgs<T> a) {
 //   op N:  thread (i = lane, q = wave) accumulates M(r0+i, c0+16q..16q+15) . y
 //   op T:  thread (j = lane, q = wave) accumulates M(r0+16q+t, c0+j) * y_j for
 //          t < 16 and the rows are summed over the wave at the end.
+// The most recent dependency is left out of that loop: its block goes to LDS
+// and wave 0 alone waits for its solution, forms its product and runs the
+// substitution, so no barrier separates the arrival of that solution from the
+// substitution.  The diagonal block is staged, scaled and the right-hand side
+// read before any waiting.
 template <typename T, int DEPTH>
 __global__ void __launch_bounds__(TNT) trsv1_kernel(TrsvArgs<T> a) {
   constexpr int LLW = LLWords<T>::n;
@@ -243,7 +259,8 @@ __global__ void __launch_bounds__(TNT) trsv1_kernel(TrsvArgs<T> a) {
   const int tid = threadIdx.x, lane = tid & 63, q = tid >> 6;
 
   __shared__ int s_ticket;
-  __shared__ T Ms[BS][BS + 1];
+  __shared__ T Ms[BS][BS + 1];     // diagonal block; wave 0 turns its rows into the scaled strict triangle
+  __shared__ T Ml[BS][BS + 1];     // block of the most recent dependency
   __shared__ T red[4][BS];
   if (tid == 0) s_ticket = atomicAdd(a.tickets + (size_t)b * a.groups, 1);
   __syncthreads();
@@ -254,15 +271,15 @@ __global__ void __launch_bounds__(TNT) trsv1_kernel(TrsvArgs<T> a) {
   const int ndep = lb;
   auto dep_block = [&](int d) { return a.upper ? (a.nblk - 1 - d) : d; };
 
-  // diagonal block into registers first (independent of everything else)
-  T dreg[16];
+  // the right-hand side and the diagonal block (independent of every other block)
+  const T rhs = (q == 0 && lane < rb) ? Y[r0 + lane] : (T)0;
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int e = tid + TNT * u;
     const int fast = e & 63, slow = e >> 6;
     int ii, jj;
     if (!a.trans) { ii = fast; jj = slow; } else { ii = slow; jj = fast; }
-    dreg[u] = (ii < rb && jj < rb) ? mel(a, M, r0 + ii, r0 + jj) : (T)0;
+    Ms[ii][jj] = (ii < rb && jj < rb) ? mel(a, M, r0 + ii, r0 + jj) : (T)0;
   }
 
   T mbuf[DEPTH][16];
@@ -286,30 +303,66 @@ __global__ void __launch_bounds__(TNT) trsv1_kernel(TrsvArgs<T> a) {
 #pragma unroll
   for (int s = 0; s < DEPTH; ++s)
     if (s < ndep) load(mbuf[s], dep_block(s));
+  __syncthreads();
+  T rdi = (T)1;
+  if (q == 0) {
+    // Substitution form: every row scaled by the reciprocal of its diagonal entry, w_l = val_l / d_l
+    // and m'_lt = m_lt / d_l on the strict triangle, zero elsewhere (and for rows past the end)
+    const T dii = (lane < rb) ? Ms[lane][lane] : (T)1;
+    rdi = a.unit ? (T)1 : (T)1 / dii;
+#pragma unroll
+    for (int t = 0; t < BS; ++t) {
+      const bool strict = a.upper ? (t > lane) : (t < lane);
+      Ms[lane][t] = (strict && lane < rb && t < rb) ? Ms[lane][t] * rdi : (T)0;
+    }
+  }
+
+  auto wait_ptr = [&](int d, const uint64_t*& ptr, bool& valid) {
+    const int cb = d < ndep ? dep_block(d) : 0, c0 = cb * BS;
+    const uint64_t* yb = slots + (size_t)cb * BS * LLW;
+    if (!a.trans) {
+      // lanes 0..15 fetch the wave's 16 solution values; readlane broadcasts them
+      ptr = yb + (size_t)(q * 16 + (lane & 15)) * LLW;
+      valid = d < ndep && lane < 16 && c0 + q * 16 + lane < a.n;
+    } else {
+      ptr = yb + (size_t)lane * LLW;
+      valid = d < ndep && c0 + lane < a.n;
+    }
+  };
   for (int d0 = 0; d0 < ndep; d0 += DEPTH) {
+    // one combined wait for the group's blocks (the most recent dependency excluded)
+    const uint64_t* ptr[DEPTH];
+    bool valid[DEPTH];
+    T yv[DEPTH];
+#pragma unroll
+    for (int s = 0; s < DEPTH; ++s) {
+      wait_ptr(d0 + s, ptr[s], valid[s]);
+      valid[s] = valid[s] && d0 + s < ndep - 1;
+    }
+    ll_wait_vals<T, DEPTH>(ptr, valid, a.flag, a.err, yv);
 #pragma unroll
     for (int s = 0; s < DEPTH; ++s) {
       const int d = d0 + s;
-      if (d < ndep) {
-        const int cb = dep_block(d), c0 = cb * BS;
-        const uint64_t* yb = slots + (size_t)cb * BS * LLW;
+      if (d < ndep - 1) {
         if (!a.trans) {
-          // lanes 0..15 fetch the wave's 16 solution values, shuffles broadcast them
-          const uint64_t* ptr[1] = {yb + (size_t)(q * 16 + (lane & 15)) * LLW};
-          const bool valid[1] = {lane < 16 && c0 + q * 16 + lane < a.n};
-          T y1[1];
-          ll_wait_vals<T, 1>(ptr, valid, a.flag, a.err, y1);
+          T p0 = (T)0, p1 = (T)0;
 #pragma unroll
-          for (int t = 0; t < 16; ++t) acc += mbuf[s][t] * __shfl(y1[0], t);
+          for (int t = 0; t < 16; t += 2) {
+            p0 += mbuf[s][t] * lane_bcast(yv[s], t);
+            p1 += mbuf[s][t + 1] * lane_bcast(yv[s], t + 1);
+          }
+          acc += p0 + p1;
         } else {
-          const uint64_t* ptr[1] = {yb + (size_t)lane * LLW};
-          const bool valid[1] = {c0 + lane < a.n};
-          T y[1];
-          ll_wait_vals<T, 1>(ptr, valid, a.flag, a.err, y);
 #pragma unroll
-          for (int t = 0; t < 16; ++t) acct[t] += mbuf[s][t] * y[0];
+          for (int t = 0; t < 16; ++t) acct[t] += mbuf[s][t] * yv[s];
         }
         if (d + DEPTH < ndep) load(mbuf[s], dep_block(d + DEPTH));
+      } else if (d == ndep - 1) {
+        // the most recent dependency's block to LDS, in (row, column) order of the operator
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          if (!a.trans) Ml[lane][q * 16 + t] = mbuf[s][t]; else Ml[q * 16 + t][lane] = mbuf[s][t];
+        }
       }
     }
   }
@@ -322,36 +375,35 @@ __global__ void __launch_bounds__(TNT) trsv1_kernel(TrsvArgs<T> a) {
       if (lane == 0) red[0][q * 16 + t] = v;
     }
   }
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int e = tid + TNT * u;
-    const int fast = e & 63, slow = e >> 6;
-    if (!a.trans) Ms[fast][slow] = dreg[u]; else Ms[slow][fast] = dreg[u];
-  }
   __syncthreads();
   if (q == 0) {
-    const T dii = (lane < rb) ? Ms[lane][lane] : (T)1;
-    const T rdi = (T)1 / dii;   // reciprocals off the serial chain
-    T rhs = (lane < rb) ? Y[r0 + lane] : (T)0;
-    T val = a.trans ? (rhs - red[0][lane]) : (rhs - ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane])));
+    T val = rhs - (a.trans ? red[0][lane] : ((red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane])));
+    if (ndep > 0) {
+      const int cb = dep_block(ndep - 1), c0 = cb * BS;
+      const uint64_t* p1[1] = {slots + ((size_t)cb * BS + lane) * LLW};
+      const bool v1[1] = {c0 + lane < a.n};
+      T y1[1];
+      ll_wait_vals<T, 1>(p1, v1, a.flag, a.err, y1);
+      T p[4] = {(T)0, (T)0, (T)0, (T)0};
+#pragma unroll
+      for (int t = 0; t < BS; ++t) p[t & 3] += Ml[lane][t] * lane_bcast(y1[0], t);
+      val -= (p[0] + p[1]) + (p[2] + p[3]);
+    }
+    // substitution: step t broadcasts the finished x_t = w_t, every lane does w_l -= m'_lt x_t
+    T mrow[BS];
+#pragma unroll
+    for (int t = 0; t < BS; ++t) mrow[t] = Ms[lane][t];
+    T w = (lane < rb) ? val * rdi : (T)0;
     if (!a.upper) {
-      for (int t = 0; t < rb; ++t) {
-        T xt = __shfl(val, t);
-        if (!a.unit) xt = xt * __shfl(rdi, t);
-        if (lane == t) val = xt;
-        if (lane > t) val -= Ms[lane][t] * xt;
-      }
+#pragma unroll
+      for (int t = 0; t < BS; ++t) w = fma(-mrow[t], lane_bcast(w, t), w);
     } else {
-      for (int t = rb - 1; t >= 0; --t) {
-        T xt = __shfl(val, t);
-        if (!a.unit) xt = xt * __shfl(rdi, t);
-        if (lane == t) val = xt;
-        if (lane < t) val -= Ms[lane][t] * xt;
-      }
+#pragma unroll
+      for (int t = BS - 1; t >= 0; --t) w = fma(-mrow[t], lane_bcast(w, t), w);
     }
     if (lane < rb) {
-      ll_store_val(slots + ((size_t)bk * BS + lane) * LLW, val, a.flag);
-      Y[r0 + lane] = val;
+      ll_store_val(slots + ((size_t)bk * BS + lane) * LLW, w, a.flag);
+      Y[r0 + lane] = w;
     }
   }
 }
@@ -387,10 +439,9 @@ size_t getrs_ws_bytes(int n, int nrhs, int batch, size_t elem) {
 
 hipError_t launch_perm(const int32_t* ipiv, int64_t strideP, int n, int32_t* perm, int64_t strideQ, int32_t* gmap,
                        int batch, hipStream_t s) {
+  (void)gmap;
   if (n <= 0 || batch <= 0) return hipSuccess;
-  const bool lds = (size_t)n * 4 <= 160 * 1024;
-  size_t sm = lds ? (size_t)n * 4 : 0;
-  hipLaunchKernelGGL(perm_kernel, dim3(batch), dim3(1024), sm, s, ipiv, strideP, n, perm, strideQ, gmap, lds ? 1 : 0);
+  hipLaunchKernelGGL(perm_kernel, dim3((n + 255) / 256, batch), dim3(256), 0, s, ipiv, strideP, n, perm, strideQ);
   return hipGetLastError();
 }
 
