@@ -130,8 +130,9 @@ def _p(t):
 
 
 def colmajor(t: torch.Tensor) -> torch.Tensor:
-    """Column-major copy of a matrix (..., n, m): strides (..., 1, n)."""
-    return t.transpose(-1, -2).contiguous().transpose(-1, -2)
+    """Column-major copy of a matrix (..., n, m): strides (..., 1, n).  Always a new
+    tensor, so that the functional API never writes into its arguments."""
+    return t.transpose(-1, -2).clone(memory_format=torch.contiguous_format).transpose(-1, -2)
 
 
 def _ld(t: torch.Tensor) -> int:

@@ -72,3 +72,18 @@ def test_product_path_refuses_to_run_without_the_library(tmp_path, monkeypatch):
     monkeypatch.setattr(b, "_lib", None)
     with pytest.raises(b.CdsError):
         b.lib()
+
+
+def test_colmajor_always_copies():
+    """The functional API factors and solves on copies: colmajor must not alias its argument,
+    also when the argument is already column-major."""
+    import torch
+    from paper_1511_07174_amd.cds import colmajor
+    a = torch.arange(12.0, dtype=torch.float64).reshape(3, 4)
+    f = colmajor(a)
+    assert f.stride() == (1, 3) and torch.equal(f, a)
+    g = colmajor(f)
+    assert g.stride() == (1, 3) and torch.equal(g, f)
+    assert g.data_ptr() != f.data_ptr()
+    g[0, 0] = 99.0
+    assert f[0, 0] == 0.0
