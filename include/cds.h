@@ -228,7 +228,10 @@ cds_status_t cds_dgesv_mixed_strided_batched(cds_handle_t handle, cds_prec_t pre
                                              float* LUlo, int64_t strideLU, int32_t* ipiv, int64_t strideP,
                                              const cds_ir_params_t* params, cds_ir_result_t* results, int64_t batch);
 /* Refinement only, from existing low-precision LU factors (e.g. for the
- * transposed solve of a gradient): op(A) X = B, op = N or T. */
+ * transposed solve of a gradient): op(A) X = B, op = N or T.  Workspace: the
+ * size cds_gesv_mixed_bufferSize reports for CDS_PREC_FP32, the same n, nrhs
+ * and batch; params->fallback is ignored (no FP64 fallback without A's
+ * factorization). */
 cds_status_t cds_dgetrs_mixed_strided_batched(cds_handle_t handle, cds_op_t op, int64_t n, int64_t nrhs,
                                               const double* A, int64_t lda, int64_t strideA, const float* LUlo,
                                               int64_t strideLU, const int32_t* ipiv, int64_t strideP,

@@ -485,7 +485,9 @@ cds_status_t cds_dgetrs_mixed_strided_batched(cds_handle_t h, cds_op_t op, int64
   if (misaligned(A, 8) || misaligned(B, 8) || misaligned(X, 8) || misaligned(LUlo, 4) || misaligned(ipiv, 4) ||
       misaligned(results, 8))
     return CDS_INVALID_VALUE;
-  cds_status_t st = need_ws(h, cds::ir_ws_bytes((int)n, (int)nrhs, (int)batch, 256, 0, 0));
+  // the same requirement as cds_gesv_mixed_bufferSize reports for these sizes
+  const int nbq = resolved_nb(getrf_nb(h, CDS_R_32F, n), n);
+  cds_status_t st = need_ws(h, cds::ir_ws_bytes((int)n, (int)nrhs, (int)batch, nbq, 0, 0));
   if (st != CDS_SUCCESS) return st;
   Ctx c = make_ctx(h);
   return cds::getrs_mixed_run(c, op == CDS_OP_T, (int)n, (int)nrhs, A, lda, strideA, LUlo,

@@ -632,6 +632,8 @@ __global__ void __launch_bounds__(256) trsm_llnu_kernel(const T* L0, T* X0, int6
 }
 
 constexpr int kLeaf = 32;
+// rows of U12 one TRSM launch stages in LDS: (rows x 33 + rows x 17) elements within 160 KiB
+template <typename T> constexpr int kTrsmMaxRows = std::is_same<T, double>::value ? 384 : 512;
 
 int default_nb(int n) {
   if (n <= 2048) return 128;
@@ -731,19 +733,43 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
     }
     if (ce > cb) {
       const int nc = ce - cb;
-      // 32 columns per workgroup
-      constexpr int CW = 32;
-      size_t sm = ((size_t)jb * (CW + 1) + (size_t)jb * 17) * sizeof(T);
-      KScope* kt = new KScope(c.timer, CDS_KC_TRSM, s, batch * (double)jb * jb * nc, 0.0);
-      if (jb <= 256)
-        hipLaunchKernelGGL((trsm_llnu_kernel<T, 16>), dim3((nc + CW - 1) / CW, batch), dim3(256), sm, s,
-                           (const T*)(A + k + (size_t)k * lda), A + k + (size_t)cb * lda, lda, strideA, jb, nc);
-      else
-        hipLaunchKernelGGL((trsm_llnu_kernel<T, 32>), dim3((nc + CW - 1) / CW, batch), dim3(256), sm, s,
-                           (const T*)(A + k + (size_t)k * lda), A + k + (size_t)cb * lda, lda, strideA, jb, nc);
-      delete kt;
-      hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
+      // U12 = L11^{-1} A12, 32 columns per workgroup, with L11 and the columns staged in LDS.
+      // Past kTrsmMaxRows rows (FP64 at nb = 512) the LDS does not hold them: the top half is
+      // solved, the bottom half updated by the GEMM and then solved.
+      auto trsm = [&](int r, int rows, T* X) -> hipError_t {
+        constexpr int CW = 32;
+        size_t sm = ((size_t)rows * (CW + 1) + (size_t)rows * 17) * sizeof(T);
+        KScope kt(c.timer, CDS_KC_TRSM, s, batch * (double)rows * rows * nc, 0.0);
+        if (rows <= 256)
+          hipLaunchKernelGGL((trsm_llnu_kernel<T, 16>), dim3((nc + CW - 1) / CW, batch), dim3(256), sm, s,
+                             (const T*)(A + r + (size_t)r * lda), X, lda, strideA, rows, nc);
+        else
+          hipLaunchKernelGGL((trsm_llnu_kernel<T, 32>), dim3((nc + CW - 1) / CW, batch), dim3(256), sm, s,
+                             (const T*)(A + r + (size_t)r * lda), X, lda, strideA, rows, nc);
+        return hipGetLastError();
+      };
+      hipError_t e;
+      if (jb <= kTrsmMaxRows<T>) {
+        e = trsm(k, jb, A + k + (size_t)cb * lda);
+        if (e != hipSuccess) return e;
+      } else {
+        const int h1 = (jb / 2 / 32) * 32, h2 = jb - h1;
+        e = trsm(k, h1, A + k + (size_t)cb * lda);
+        if (e != hipSuccess) return e;
+        GemmArgs<T> gt;
+        gt.m = h2; gt.n = nc; gt.k = h1;
+        gt.A = A + (k + h1) + (size_t)k * lda; gt.lda = lda; gt.strideA = strideA;
+        gt.B = A + k + (size_t)cb * lda; gt.ldb = lda; gt.strideB = strideA;
+        gt.C = A + (k + h1) + (size_t)cb * lda; gt.ldc = lda; gt.strideC = strideA;
+        gt.alpha = (T)-1; gt.transB = 0; gt.lower = 0; gt.scale_exp = nullptr; gt.guard = nullptr;
+        {
+          KScope kt(c.timer, CDS_KC_TRSM, s, batch * 2.0 * h2 * (double)nc * h1, 0.0);
+          e = launch_gemm<T>(gt, batch, 0, s);
+        }
+        if (e != hipSuccess) return e;
+        e = trsm(k + h1, h2, A + (k + h1) + (size_t)cb * lda);
+        if (e != hipSuccess) return e;
+      }
       const int mrem = n - k - jb;
       const int* sc = nullptr;
       if (mrem > 0 && mode == 2 && scale_exp != nullptr) {

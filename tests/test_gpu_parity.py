@@ -65,6 +65,30 @@ def test_getrf_dyadic_bitwise(cds, n):
     no_device_error(cds)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("nb,lookahead", [(32, 1), (64, 1), (128, 0), (192, 1), (384, 1), (512, 1), (512, 0)])
+def test_getrf_block_sizes(cds, nb, lookahead, dtype):
+    """Every block size (including the split TRSM beyond 384 FP64 rows) and both schedules give the
+    exact factors of the dyadic construction."""
+    from paper_1511_07174_amd.cds import OPT_NB, OPT_LOOKAHEAD
+    n = 1100
+    A, L, U, perm = synth.dyadic_plu(n, 77)
+    h = cds.handle()
+    h.set_option(OPT_NB, nb)
+    h.set_option(OPT_LOOKAHEAD, lookahead)
+    try:
+        LU, ipiv, info = cds.getrf(to_dev(A, dtype))
+        LUh = host(LU).astype(np.float64)
+    finally:
+        h.set_option(OPT_NB, 0)
+        h.set_option(OPT_LOOKAHEAD, 1)
+    Lr, Ur = oracle.unpack_lu(LUh)
+    assert int(info.item()) == 0
+    assert np.array_equal(host(ipiv), synth.perm_to_ipiv(perm))
+    assert np.array_equal(Lr, L) and np.array_equal(Ur, U)
+    no_device_error(cds)
+
+
 @pytest.mark.parametrize("n", [5, 53])
 def test_getrf_wilkinson_ties(cds, n):
     A = synth.wilkinson(n)
