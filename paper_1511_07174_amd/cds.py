@@ -362,7 +362,12 @@ _default_handle = None
 
 
 def handle() -> Handle:
+    """The package's handle; on creation it installs the tuning table (see tune.py)."""
     global _default_handle
     if _default_handle is None:
         _default_handle = Handle()
+        from . import tune
+        path = tune.default_table_path()
+        if path.lower() != "none" and os.path.exists(path):
+            tune.load_table(path, _default_handle)
     return _default_handle

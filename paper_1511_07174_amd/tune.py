@@ -5,12 +5,18 @@ persists a JSON table; ``load_table`` installs a table into a handle through
 ``cds_tune_set``.  Tuned quantities:
 
 * ``getrf_nb`` (per dtype, per n bucket): block size of the blocked LU, from
-  {128, 256, 512};
-* ``potrf_nb``: same for Cholesky;
+  {128, 192, 256, 384};
+* ``potrf_nb``: same for Cholesky, from {128, 256, 384};
 * ``vbatch_tile`` (per n bucket): block-column width of the in-workgroup
   Cholesky of the batched SPD solver, 16 or 32.
 
-Inputs are seeded synthetic matrices of the tuned sizes.
+Inputs are seeded synthetic matrices of the tuned sizes.  The entry of a size
+bucket applies to every n up to the bucket's size; the largest bucket's value
+is repeated for all larger n.  ``handle()`` installs the table shipped with the
+package (``tune_gfx950.json``) when it exists; ``CDS_TUNE_FILE`` names another
+table, or ``none`` to run on the built-in defaults.
+
+Run: ``python -m paper_1511_07174_amd.tune --out tune_gfx950.json``.
 """
 from __future__ import annotations
 
@@ -40,7 +46,7 @@ def _timeit(fn, reps=2):
     return best
 
 
-def tune_getrf(sizes=(4096, 8192, 16384), dtypes=("f64", "f32"), candidates=(128, 256, 512), seed=0):
+def tune_getrf(sizes=(2048, 4096, 8192, 16384), dtypes=("f64", "f32"), candidates=(128, 192, 256, 384), seed=0):
     h = cds.handle()
     dev = torch.device("cuda", torch.cuda.current_device())
     g = torch.Generator(device=dev).manual_seed(seed)
@@ -66,6 +72,38 @@ def tune_getrf(sizes=(4096, 8192, 16384), dtypes=("f64", "f32"), candidates=(128
             h.set_option(cds.OPT_NB, 0)
             entries.append({"key": "getrf_nb", "dtype": dt, "n_max": n, "value": best[0]})
             del A, LU
+        entries.append({"key": "getrf_nb", "dtype": dt, "n_max": 2 ** 31 - 1, "value": entries[-1]["value"]})
+    return entries, timings
+
+
+def tune_potrf(sizes=(2048, 4096, 8192, 16384), dtypes=("f64", "f32"), candidates=(128, 256, 384), seed=1):
+    h = cds.handle()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    g = torch.Generator(device=dev).manual_seed(seed)
+    entries, timings = [], []
+    for dt in dtypes:
+        tdt = torch.float64 if dt == "f64" else torch.float32
+        for n in sizes:
+            M = torch.rand(n, n, generator=g, device=dev, dtype=torch.float64) * 2 - 1
+            A = colmajor((M @ M.T / n + torch.eye(n, device=dev, dtype=torch.float64)).to(tdt))
+            del M
+            L = torch.empty_like(A)
+            info = torch.zeros(1, dtype=torch.int32, device=dev)
+            best = None
+            for nb in candidates:
+                h.set_option(cds.OPT_NB, nb)
+
+                def run():
+                    L.copy_(A)
+                    h.potrf_(L, info)
+                t = _timeit(run)
+                timings.append({"op": "potrf", "dtype": dt, "n": n, "nb": nb, "ms": t * 1e3})
+                if best is None or t < best[1]:
+                    best = (nb, t)
+            h.set_option(cds.OPT_NB, 0)
+            entries.append({"key": "potrf_nb", "dtype": dt, "n_max": n, "value": best[0]})
+            del A, L
+        entries.append({"key": "potrf_nb", "dtype": dt, "n_max": 2 ** 31 - 1, "value": entries[-1]["value"]})
     return entries, timings
 
 
@@ -120,3 +158,26 @@ def load_table(path, handle=None):
 
 def default_table_path():
     return os.environ.get("CDS_TUNE_FILE", os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_gfx950.json"))
+
+
+def main(argv=None):
+    import argparse
+    ap = argparse.ArgumentParser(description="time the candidate block sizes and tile widths, save the table")
+    ap.add_argument("--out", default=default_table_path())
+    ap.add_argument("--quick", action="store_true", help="only n <= 8192")
+    a = ap.parse_args(argv)
+    h = cds.handle()
+    h.tune_clear()
+    sizes = (2048, 4096, 8192) if a.quick else (2048, 4096, 8192, 16384)
+    e1, t1 = tune_getrf(sizes=sizes)
+    print("getrf", e1, flush=True)
+    e2, t2 = tune_potrf(sizes=sizes)
+    print("potrf", e2, flush=True)
+    e3, t3 = tune_vbatched()
+    print("vbatched", e3, flush=True)
+    save_table(a.out, e1 + e2 + e3, t1 + t2 + t3)
+    print("saved", a.out, flush=True)
+
+
+if __name__ == "__main__":
+    main()
