@@ -4,8 +4,8 @@
 //                  sub-blocks; the first non-positive (or NaN) pivot records
 //                  info and stops the factorization (every later kernel of the
 //                  call sees info != 0 and returns).
-//   trsm_rlt_kernel  L21 = A21 L11^{-T}, rows in LDS, 16-column blocks.
-// The trailing update A22 -= L21 L21^T is the MFMA GEMM in lower-tile mode.
+// L21 = A21 L11^{-T} is the MFMA triangular solve of trsm.hip on the transposed
+// rows; the trailing update A22 -= L21 L21^T is the MFMA GEMM in lower-tile mode.
 #include "common.hpp"
 #include "kernels.hpp"
 #include "mixed.hpp"
@@ -103,57 +103,13 @@ __global__ void __launch_bounds__(256) potf2_kernel(T* A, int64_t lda, int k, in
   }
 }
 
-// L21 = A21 L11^{-T} for the rows [k+jb, n) of the panel columns [k, k+jb).
-// Workgroup: RW rows in LDS; 16-column blocks: solve the block row-wise, then
-// update the columns to its right.
-template <typename T>
-__global__ void __launch_bounds__(256) trsm_rlt_kernel(T* A, int64_t lda, int k, int jb, int nrows, int RW,
-                                                       const int32_t* info) {
-  if (*info != 0) return;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* X = reinterpret_cast<T*>(smem_raw);  // [RW][jb+1]
-  const int P = jb + 1;
-  const T* L = A + k + (size_t)k * lda;
-  T* B = A + (k + jb) + (size_t)k * lda;
-  const int r0 = blockIdx.x * RW;
-  const int rw = min(RW, nrows - r0);
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < rw * jb; idx += 256) {
-    const int r = idx % rw, c = idx / rw;
-    X[r * P + c] = B[(r0 + r) + (size_t)c * lda];
-  }
-  __syncthreads();
-  constexpr int CB = 16;
-  for (int c0 = 0; c0 < jb; c0 += CB) {
-    const int cb = min(CB, jb - c0);
-    if (tid < rw) {
-      for (int j = 0; j < cb; ++j) {
-        T v = X[tid * P + c0 + j];
-        for (int t = 0; t < j; ++t) v -= X[tid * P + c0 + t] * L[(c0 + j) + (size_t)(c0 + t) * lda];
-        X[tid * P + c0 + j] = v / L[(c0 + j) + (size_t)(c0 + j) * lda];
-      }
-    }
-    __syncthreads();
-    const int right = jb - c0 - cb;
-    for (int idx = tid; idx < rw * right; idx += 256) {
-      const int r = idx % rw, j = c0 + cb + idx / rw;
-      T v = X[r * P + j];
-      for (int t = 0; t < cb; ++t) v -= X[r * P + c0 + t] * L[j + (size_t)(c0 + t) * lda];
-      X[r * P + j] = v;
-    }
-    __syncthreads();
-  }
-  for (int idx = tid; idx < rw * jb; idx += 256) {
-    const int r = idx % rw, c = idx / rw;
-    B[(r0 + r) + (size_t)c * lda] = X[r * P + c];
-  }
-}
-
 }  // namespace
 
 size_t potrf_ws_bytes(int n, int nb, size_t elem) {
-  (void)n; (void)nb; (void)elem;
-  return kErrRegion;
+  (void)n; (void)nb;
+  // the diagonal-block inverses of L11 for the TRSM, sized for the largest block (512)
+  (void)elem;
+  return kErrRegion + ((trsm16_inv_elems(512) * sizeof(double) + 255) & ~(size_t)255);
 }
 
 template <typename T>
@@ -173,14 +129,16 @@ cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int
     if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
     const int rem = n - k - jb;
     if (rem <= 0) break;
-    int RW = (int)std::max<int64_t>(8, std::min<int64_t>(64, 65536 / ((int64_t)(jb + 1) * sizeof(T))));
-    size_t sm = (size_t)RW * (jb + 1) * sizeof(T);
     {
+      // L21 = A21 L11^{-T}: the transposed column solve L11 L21^T = A21^T on MFMA tiles
       KScope ks(c.timer, CDS_KC_TRSM, s, (double)jb * jb * rem, 0.0);
-      hipLaunchKernelGGL((trsm_rlt_kernel<T>), dim3((rem + RW - 1) / RW), dim3(256), sm, s, A, lda, k, jb, rem, RW,
-                         (const int32_t*)info);
+      double* linv = (double*)((char*)c.ws + kErrRegion);
+      if (launch_diag_inv16<T>(A + k + (size_t)k * lda, lda, 0, jb, 0, linv, 0, 1, s) != hipSuccess)
+        return CDS_HIP_ERROR;
+      if (launch_trsm16<T>(A + k + (size_t)k * lda, lda, 0, linv, 0, A + (k + jb) + (size_t)k * lda, lda, 0, jb, rem,
+                           1, 1, info, s) != hipSuccess)
+        return CDS_HIP_ERROR;
     }
-    if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
     GemmArgs<T> g;
     g.m = rem; g.n = rem; g.k = jb;
     g.A = A + (k + jb) + (size_t)k * lda; g.lda = lda; g.strideA = 0;

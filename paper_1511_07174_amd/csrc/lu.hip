@@ -202,10 +202,10 @@ __device__ void compact_entries(const int* s_dst, const int* s_src, int ne, int 
 // leaf, the leaf's interchanges move rows between workgroups in one
 // publish/consume round of flag+payload words, every workgroup forms
 // U_right = L11^{-1} P_top for the right part of the panel, and updates its own
-// rows with an MFMA product; the first W updated columns (the next leaf) stay in
-// LDS.
+// rows with an MFMA product.  About 70 KiB of LDS (FP64), so that a panel
+// workgroup fits beside a trailing-update workgroup on one compute unit.
 template <typename T, int W>
-__global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
+__global__ void __launch_bounds__(PNT, 2) panel_kernel(PanelArgs<T> P) {
   constexpr int LLW = LLWords<T>::n;
   constexpr bool F64 = std::is_same<T, double>::value;
   typedef typename std::conditional<F64, d4, f4>::type acc_t;
@@ -222,8 +222,9 @@ __global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
   SlotLayout<T, W> L{P.G, jb};
   const int row = g * PNT + tid;
   const bool own = row < m;
+  // the panel is the critical path; its waves win issue arbitration over a co-resident trailing update
+  __builtin_amdgcn_s_setprio(3);
 
-  __shared__ T lf[PNT][W + 1];      // this workgroup's rows of the leaf (the MFMA B operand, the next leaf)
   __shared__ T rowbuf[4][W];        // per-wave best candidate row
   __shared__ T jbuf[W];             // row j (owner workgroup)
   __shared__ T red_mag[4];
@@ -245,14 +246,8 @@ __global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
     const int c1 = c0 + wl;
     const bool act = own && row >= c0;
     T v[W];
-    if (c0 == 0) {
 #pragma unroll
-      for (int cc = 0; cc < W; ++cc) v[cc] = (act && cc < wl) ? A[row + (size_t)cc * lda] : (T)0;
-    } else {
-      // written by this thread's own wave at the end of the previous leaf
-#pragma unroll
-      for (int cc = 0; cc < W; ++cc) v[cc] = (act && cc < wl) ? lf[tid][cc] : (T)0;
-    }
+    for (int cc = 0; cc < W; ++cc) v[cc] = (act && cc < wl) ? A[row + (size_t)(c0 + cc) * lda] : (T)0;
     for (int cc = 0; cc < wl; ++cc) {
       const int j = c0 + cc;
       const int par = j & 1;
@@ -307,8 +302,6 @@ __global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
       for (int cc = 0; cc < W; ++cc)
         if (cc < wl) A[row + (size_t)(c0 + cc) * lda] = v[cc];
     }
-#pragma unroll
-    for (int cc = 0; cc < W; ++cc) lf[tid][cc] = v[cc];
     __syncthreads();
     if (wave == 0) {
       const int ne0 = compose_leaf<W>(s_piv, c0, wl, s_dst, s_src, &s_ne);
@@ -327,7 +320,7 @@ __global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
       if (tid == 0) pair_cnt[leafc] = ne;
     }
     if (nv == 0) continue;
-    constexpr int SB = 16;
+    constexpr int SB = 8;
     // publish the non-leaf columns of the rows this workgroup is the source of
     {
       const int nown = s_nown;
@@ -357,13 +350,23 @@ __global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
     }
     __syncthreads();   // every read of a source row of this workgroup precedes the writes below
     const int ndl = s_ndl;
-    // the MFMA B operand (L21 of this wave's rows), read before the next leaf overwrites lf
+    // the MFMA B operand, L21 of this wave's rows: lane l takes column 4 kc + l / 16 of the row held
+    // by lane 16 rt + l % 16 (four lane shuffles, one per column offset, and a select)
     const int wr = wave * 64;                      // first row of this wave within the workgroup
     T bop[4][W / 4];
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-      for (int kc = 0; kc < W / 4; ++kc) bop[rt][kc] = lf[wr + rt * 16 + (lane & 15)][4 * kc + (lane >> 4)];
+      for (int kc = 0; kc < W / 4; ++kc) {
+        const int src = rt * 16 + (lane & 15);
+        T sel = (T)0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const T t = __shfl(v[4 * kc + q], src, kWave);
+          sel = ((lane >> 4) == q) ? t : sel;
+        }
+        bop[rt][kc] = sel;
+      }
     bool first = true;
     // the first pass also takes the rows this workgroup receives, so it runs for the last leaf too
     for (int x0 = c1; x0 < jb || first; x0 += PCH, first = false) {
@@ -434,17 +437,15 @@ __global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
       }
       // rows >= c1 of this wave: C[rows, cols] -= L21[rows, :] U_right[:, cols] on 16x16x4 MFMA tiles,
       // computed transposed (D = -U^T L21^T) so that a lane's accumulators run down a column.
-      // Sub-chunks of 32 columns; the one holding the next leaf goes last and into lf.
+      // Sub-chunks of 32 columns.
       {
         const int nsub = (cw + 31) / 32;
-        for (int si = 0; si < nsub; ++si) {
-          const int sub = first ? (si + 1) % nsub : si;   // the next leaf's columns last
-          const bool to_lds = first && sub == 0;
+        for (int sub = 0; sub < nsub; ++sub) {
           const int xs = x0 + sub * 32;
           const int cws = min(32, x0 + cw - xs);
-          acc_t acc[2][4];
 #pragma unroll
-          for (int ct = 0; ct < 2; ++ct)
+          for (int ct = 0; ct < 2; ++ct) {
+            acc_t acc[4];
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
@@ -452,37 +453,28 @@ __global__ void __launch_bounds__(PNT) panel_kernel(PanelArgs<T> P) {
                 const int ci = ct * 16 + (F64 ? ((lane >> 4) + 4 * vq) : (4 * (lane >> 4) + vq));
                 const int rr = g * PNT + wr + rt * 16 + (lane & 15);
                 const bool ok = rr < m && rr >= c1 && ci < cws;
-                acc[ct][rt][vq] = ok ? A[rr + (size_t)(xs + ci) * lda] : (T)0;
+                acc[rt][vq] = ok ? A[rr + (size_t)(xs + ci) * lda] : (T)0;
               }
 #pragma unroll
-          for (int kc = 0; kc < W / 4; ++kc) {
-#pragma unroll
-            for (int ct = 0; ct < 2; ++ct) {
+            for (int kc = 0; kc < W / 4; ++kc) {
               const T aop = -Ubuf[4 * kc + (lane >> 4)][xs - x0 + ct * 16 + (lane & 15)];
 #pragma unroll
               for (int rt = 0; rt < 4; ++rt) {
                 if constexpr (F64)
-                  acc[ct][rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop[rt][kc], acc[ct][rt], 0, 0, 0);
+                  acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop[rt][kc], acc[rt], 0, 0, 0);
                 else
-                  acc[ct][rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop[rt][kc], acc[ct][rt], 0, 0, 0);
+                  acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop[rt][kc], acc[rt], 0, 0, 0);
               }
             }
-          }
-#pragma unroll
-          for (int ct = 0; ct < 2; ++ct)
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
               for (int vq = 0; vq < 4; ++vq) {
                 const int ci = ct * 16 + (F64 ? ((lane >> 4) + 4 * vq) : (4 * (lane >> 4) + vq));
-                const int rl = wr + rt * 16 + (lane & 15);
-                const int rr = g * PNT + rl;
-                if (to_lds) {
-                  lf[rl][ci] = acc[ct][rt][vq];
-                } else if (rr < m && rr >= c1 && ci < cws) {
-                  A[rr + (size_t)(xs + ci) * lda] = acc[ct][rt][vq];
-                }
+                const int rr = g * PNT + wr + rt * 16 + (lane & 15);
+                if (rr < m && rr >= c1 && ci < cws) A[rr + (size_t)(xs + ci) * lda] = acc[rt][vq];
               }
+          }
         }
       }
       __syncthreads();   // Ubuf is reloaded by the next chunk
@@ -528,112 +520,7 @@ __global__ void __launch_bounds__(256) laswp_kernel(T* A0, int64_t lda, int64_t 
   }
 }
 
-// U12 = L11^{-1} A12: L11 = jb x jb unit lower at L (ld lda), A12 = jb x ncols at X (ld lda).
-// A workgroup solves CW = 32 columns held in LDS, in 16-row blocks.  For each
-// block, the 16 columns of L below the diagonal block are staged in LDS (the
-// next block's prefetched into registers while the current one is used); the
-// 16 x 16 unit-lower diagonal solve runs with one column per lane; the update
-// of the rows below is a (rows x 16) x (16 x 32) product on MFMA 16x16x4 tiles
-// with operands read from LDS (the LDS operand rate would bound a VALU update).
-template <typename T, int PRE>
-__global__ void __launch_bounds__(256) trsm_llnu_kernel(const T* L0, T* X0, int64_t lda, int64_t strideA, int jb,
-                                                        int ncols) {
-  constexpr int CW = 32, RB = 16;
-  constexpr int PX = CW + 1;              // X pitch
-  constexpr int PL = RB + 1;              // Lb pitch
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* X = reinterpret_cast<T*>(smem_raw);  // [jb][PX]
-  T* Lb = X + (size_t)jb * PX;            // [jb][PL], rows relative to the block start
-  const int b = blockIdx.y;
-  const T* L = L0 + (size_t)b * strideA;
-  T* Xg = X0 + (size_t)b * strideA;
-  const int c0 = blockIdx.x * CW;
-  const int cw = min(CW, ncols - c0);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int idx = tid; idx < jb * CW; idx += 256) {
-    const int c = idx / jb, r = idx % jb;
-    X[r * PX + c] = (c < cw) ? Xg[r + (size_t)(c0 + c) * lda] : (T)0;
-  }
-  T pre[PRE];
-  auto prefetch = [&](int r0) {
-    const int rows = jb - r0, rbk = min(RB, jb - r0);
-#pragma unroll
-    for (int u = 0; u < PRE; ++u) {
-      const int e = tid + 256 * u;
-      const int i = e % rows, t = e / rows;
-      pre[u] = (rows > 0 && t < rbk && e < rows * rbk) ? L[(r0 + i) + (size_t)(r0 + t) * lda] : (T)0;
-    }
-  };
-  prefetch(0);
-  for (int r0 = 0; r0 < jb; r0 += RB) {
-    const int rb = min(RB, jb - r0), rows = jb - r0;
-    __syncthreads();   // the previous block is done with Lb and X
-#pragma unroll
-    for (int u = 0; u < PRE; ++u) {
-      const int e = tid + 256 * u;
-      if (e < rows * rb) Lb[(e % rows) * PL + e / rows] = pre[u];
-    }
-    if (r0 + RB < jb) prefetch(r0 + RB);
-    __syncthreads();
-    // diagonal block: lane = column, rows in registers
-    if (wave == 0 && lane < CW) {
-      T x[RB];
-#pragma unroll
-      for (int i = 0; i < RB; ++i) x[i] = (i < rb) ? X[(r0 + i) * PX + lane] : (T)0;
-#pragma unroll
-      for (int i = 1; i < RB; ++i) {
-        T s = x[i];
-#pragma unroll
-        for (int t = 0; t < i; ++t) s -= Lb[i * PL + t] * x[t];
-        x[i] = s;
-      }
-#pragma unroll
-      for (int i = 0; i < RB; ++i)
-        if (i < rb) X[(r0 + i) * PX + lane] = x[i];
-    }
-    __syncthreads();
-    // rows below: tiles of 16 rows x 16 columns, round-robin over the waves
-    const int nbelow = rows - rb;
-    const int rtiles = (nbelow + 15) / 16;
-    typedef typename std::conditional<std::is_same<T, double>::value, d4, f4>::type acc_t;
-    for (int tile = wave; tile < rtiles * (CW / 16); tile += 4) {
-      const int ti = tile / (CW / 16), tj = tile % (CW / 16);
-      const int rbase = rb + ti * 16;       // row offset within the block (relative to r0)
-      acc_t acc;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = std::is_same<T, double>::value ? (lane / 16 + 4 * v) : (4 * (lane / 16) + v);
-        const int rr = rbase + r;
-        acc[v] = (rr < rows) ? X[(r0 + rr) * PX + tj * 16 + (lane & 15)] : (T)0;
-      }
-#pragma unroll
-      for (int kc = 0; kc < RB / 4; ++kc) {
-        const int ar = rbase + (lane & 15), ak = kc * 4 + lane / 16;
-        const T af = (ar < rows && ak < rb) ? -Lb[ar * PL + ak] : (T)0;
-        const T bf = (ak < rb) ? X[(r0 + ak) * PX + tj * 16 + (lane & 15)] : (T)0;
-        if constexpr (std::is_same<T, double>::value)
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, acc, 0, 0, 0);
-        else
-          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf, acc, 0, 0, 0);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = std::is_same<T, double>::value ? (lane / 16 + 4 * v) : (4 * (lane / 16) + v);
-        const int rr = rbase + r;
-        if (rr < rows) X[(r0 + rr) * PX + tj * 16 + (lane & 15)] = acc[v];
-      }
-    }
-  }
-  __syncthreads();
-  for (int idx = tid; idx < jb * cw; idx += 256) {
-    const int c = idx / jb, r = idx % jb;
-    Xg[r + (size_t)(c0 + c) * lda] = X[r * PX + c];
-  }
-}
-
 constexpr int kLeaf = 32;
-// rows of U12 one TRSM launch stages in LDS: (rows x 33 + rows x 17) elements within 160 KiB
-template <typename T> constexpr int kTrsmMaxRows = std::is_same<T, double>::value ? 384 : 512;
 
 int default_nb(int n) {
   if (n <= 2048) return 128;
@@ -654,8 +541,9 @@ size_t getrf_ws_bytes(int n, int nb, int leaf, int batch, size_t elem) {
   size_t slots = (size_t)slot_words * 8 * batch;
   size_t pairs = (size_t)2 * batch * nleaves * 3 * kLeaf * sizeof(int2);
   size_t cnts = (size_t)2 * batch * nleaves * sizeof(int);
+  size_t inv = (size_t)2 * batch * trsm16_inv_elems(jb) * sizeof(double);   // L11 diagonal-block inverses, by parity
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  return kErrRegion + al(slots) + al(pairs) + al(cnts);
+  return kErrRegion + al(slots) + al(pairs) + al(cnts) + al(inv);
 }
 
 template <typename T>
@@ -685,6 +573,9 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
   int2* pairs = (int2*)(base + slots_b);
   size_t pairs_b = al((size_t)2 * batch * nleaves * 3 * W * sizeof(int2));
   int* cnts = (int*)(base + slots_b + pairs_b);
+  size_t cnts_b = al((size_t)2 * batch * nleaves * sizeof(int));
+  double* linv = (double*)(base + slots_b + pairs_b + cnts_b);
+  const int64_t inv_stride = (int64_t)trsm16_inv_elems(jbmax);   // per matrix
   const int64_t pairs_stride = (int64_t)nleaves * 3 * W;   // per matrix per parity
 
   hipStream_t s0 = c.s0, s1 = c.s1;
@@ -711,10 +602,17 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
     P.err = c.err;
     P.G = (n - k + PNT - 1) / PNT;
     const double m = n - k;
-    KScope ks(c.timer, CDS_KC_PANEL, s, batch * (m * jb * jb - (double)jb * jb * jb / 3.0),
-              batch * 2.0 * m * jb * sizeof(T));
-    hipLaunchKernelGGL((panel_kernel<T, kLeaf>), dim3(P.G, batch), dim3(PNT), 0, s, P);
-    return hipGetLastError();
+    {
+      KScope ks(c.timer, CDS_KC_PANEL, s, batch * (m * jb * jb - (double)jb * jb * jb / 3.0),
+                batch * 2.0 * m * jb * sizeof(T));
+      hipLaunchKernelGGL((panel_kernel<T, kLeaf>), dim3(P.G, batch), dim3(PNT), 0, s, P);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // inverses of L11's 16 x 16 diagonal blocks for this panel's TRSMs
+    KScope kt(c.timer, CDS_KC_TRSM, s, 0.0, 0.0);
+    return launch_diag_inv16<T>(A + k + (size_t)k * lda, lda, strideA, jb, 1, linv + (size_t)parity * batch * inv_stride,
+                                inv_stride, batch, s);
   };
   // interchanges + trsm + gemm on columns [cb, ce) for the panel at k (width jb)
   auto update = [&](int k, int jb, int parity, int cb, int ce, bool left, hipStream_t s) -> hipError_t {
@@ -733,43 +631,14 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
     }
     if (ce > cb) {
       const int nc = ce - cb;
-      // U12 = L11^{-1} A12, 32 columns per workgroup, with L11 and the columns staged in LDS.
-      // Past kTrsmMaxRows rows (FP64 at nb = 512) the LDS does not hold them: the top half is
-      // solved, the bottom half updated by the GEMM and then solved.
-      auto trsm = [&](int r, int rows, T* X) -> hipError_t {
-        constexpr int CW = 32;
-        size_t sm = ((size_t)rows * (CW + 1) + (size_t)rows * 17) * sizeof(T);
-        KScope kt(c.timer, CDS_KC_TRSM, s, batch * (double)rows * rows * nc, 0.0);
-        if (rows <= 256)
-          hipLaunchKernelGGL((trsm_llnu_kernel<T, 16>), dim3((nc + CW - 1) / CW, batch), dim3(256), sm, s,
-                             (const T*)(A + r + (size_t)r * lda), X, lda, strideA, rows, nc);
-        else
-          hipLaunchKernelGGL((trsm_llnu_kernel<T, 32>), dim3((nc + CW - 1) / CW, batch), dim3(256), sm, s,
-                             (const T*)(A + r + (size_t)r * lda), X, lda, strideA, rows, nc);
-        return hipGetLastError();
-      };
+      // U12 = L11^{-1} A12 on MFMA tiles, from the panel's diagonal-block inverses
       hipError_t e;
-      if (jb <= kTrsmMaxRows<T>) {
-        e = trsm(k, jb, A + k + (size_t)cb * lda);
-        if (e != hipSuccess) return e;
-      } else {
-        const int h1 = (jb / 2 / 32) * 32, h2 = jb - h1;
-        e = trsm(k, h1, A + k + (size_t)cb * lda);
-        if (e != hipSuccess) return e;
-        GemmArgs<T> gt;
-        gt.m = h2; gt.n = nc; gt.k = h1;
-        gt.A = A + (k + h1) + (size_t)k * lda; gt.lda = lda; gt.strideA = strideA;
-        gt.B = A + k + (size_t)cb * lda; gt.ldb = lda; gt.strideB = strideA;
-        gt.C = A + (k + h1) + (size_t)cb * lda; gt.ldc = lda; gt.strideC = strideA;
-        gt.alpha = (T)-1; gt.transB = 0; gt.lower = 0; gt.scale_exp = nullptr; gt.guard = nullptr;
-        {
-          KScope kt(c.timer, CDS_KC_TRSM, s, batch * 2.0 * h2 * (double)nc * h1, 0.0);
-          e = launch_gemm<T>(gt, batch, 0, s);
-        }
-        if (e != hipSuccess) return e;
-        e = trsm(k + h1, h2, A + (k + h1) + (size_t)cb * lda);
-        if (e != hipSuccess) return e;
+      {
+        KScope kt(c.timer, CDS_KC_TRSM, s, batch * (double)jb * jb * nc, 0.0);
+        e = launch_trsm16<T>(A + k + (size_t)k * lda, lda, strideA, linv + (size_t)parity * batch * inv_stride,
+                             inv_stride, A + k + (size_t)cb * lda, lda, strideA, jb, nc, 0, batch, nullptr, s);
       }
+      if (e != hipSuccess) return e;
       const int mrem = n - k - jb;
       const int* sc = nullptr;
       if (mrem > 0 && mode == 2 && scale_exp != nullptr) {
