@@ -15,6 +15,12 @@ from events around each launch on its own stream during the timed steps) and
 the CPU oracle's rate on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 16384]
+
+Other workloads (one JSON line each; the default above is the headline):
+  --workload chol      Cholesky potrf + potrs and the FP32 + FP64-refinement SPD solve, n = 16384
+  --workload adjoint   differentiable solve, batch 64 x n = 2048 (forward + backward), FP64 and FP32+IR
+  --workload vbatched  2000 SPD systems, n ~ U{32..1024}, nrhs 4, one persistent launch
+  --workload kernels   per-kernel-class times and rates of FP64 and FP32 getrf + getrs at n = 16384
 """
 from __future__ import annotations
 
@@ -52,6 +58,185 @@ def cpu_baseline(n_sample: int):
             "eta": oracle.eta_inf(A, x, B[:, 0])}
 
 
+def _events_time(fn, reps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    import numpy as np
+    return float(np.median(ts)), float(min(ts)), float(max(ts))
+
+
+def _line(d):
+    print(json.dumps(d), flush=True)
+
+
+def bench_chol(args):
+    """Cholesky at n = 16384: A = M M^T / n + I with M ~ U[-1,1] (generated on the device from a seeded
+    generator), potrf GFLOP/s (1/3 n^3), potrs time, and the FP32 Cholesky + FP64 refinement solve."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_1511_07174_amd as cds
+    from paper_1511_07174_amd.cds import decode_results
+    dev = torch.device("cuda", 0)
+    n = args.n
+    g = torch.Generator(device=dev).manual_seed(6)
+    M = torch.rand(n, n, generator=g, dtype=torch.float64, device=dev) * 2 - 1
+    A = cds.colmajor(M @ M.T / n + torch.eye(n, dtype=torch.float64, device=dev))
+    del M
+    b = torch.rand(n, generator=g, dtype=torch.float64, device=dev) * 2 - 1
+    h = cds.handle()
+    L = torch.empty_like(A)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    tc, _, _ = _events_time(lambda: L.copy_(A), 3, 1)
+    t, tmin, tmax = _events_time(lambda: (L.copy_(A), h.potrf_(L, info)), args.steps, args.warmup)
+    t -= tc
+    x = torch.empty_like(b)
+    ts, _, _ = _events_time(lambda: (x.copy_(b), h.potrs_(L, x)), args.steps, args.warmup)
+    X = torch.zeros_like(b)
+    Llo = torch.empty(n * n, dtype=torch.float32, device=dev)
+    res = torch.zeros(cds.cds.IR_RESULT_BYTES, dtype=torch.uint8, device=dev)
+    prm = cds.default_params(tol=1e-14, success_tol=1e-14, host_check=1)
+    tm, _, _ = _events_time(lambda: h.posv_mixed(A, b, X, Llo, res, precision="fp32", params=prm), args.steps,
+                            args.warmup)
+    r = decode_results(res)[0]
+    oracle.build()
+    Ah = np.asfortranarray(A.cpu().numpy())
+    bh = b.cpu().numpy()
+    eta64 = oracle.eta_inf(Ah, x.cpu().numpy(), bh)
+    eta_mixed = oracle.eta_inf(Ah, X.cpu().numpy(), bh)
+    _line({"metric": "Cholesky potrf GFLOP/s (1/3 n^3) and SPD solve times", "workload": "chol", "n": n,
+           "info": int(info.item()), "potrf_ms": round(t * 1e3, 3), "potrf_gflops": round(n ** 3 / 3 / t / 1e9, 1),
+           "potrf_frac_of_f64_peak": round(n ** 3 / 3 / t / 78.6e12, 4), "potrs_ms": round(ts * 1e3, 3),
+           "potrs_GBps": round(8.0 * n * n / ts / 1e9, 1), "fp64_eta": eta64,
+           "posv_fp32_ir_ms": round(tm * 1e3, 3), "posv_ir_iters": r.iters, "posv_eta": eta_mixed,
+           "posv_converged": bool(r.converged), "data": "synthetic, device generator seed 6"})
+
+
+def bench_adjoint(args):
+    """Batched differentiable solve: 64 systems of n = 2048, A, b, w ~ U[-1,1]; loss = sum(w x); forward
+    (batched getrf + getrs, or FP32 + FP64 refinement) and backward (A^-T w, -bbar x^T) timed apart."""
+    import torch
+    import paper_1511_07174_amd as cds
+    dev = torch.device("cuda", 0)
+    batch, n = 64, 2048
+    g = torch.Generator(device=dev).manual_seed(20)
+    A0 = torch.rand(batch, n, n, generator=g, dtype=torch.float64, device=dev) * 2 - 1
+    b0 = torch.rand(batch, n, generator=g, dtype=torch.float64, device=dev) * 2 - 1
+    w = torch.rand(batch, n, generator=g, dtype=torch.float64, device=dev) * 2 - 1
+    out = {"metric": "batched differentiable solve, forward and backward ms", "workload": "adjoint",
+           "batch": batch, "n": n, "data": "synthetic, device generator seed 20"}
+    for prec in ("fp64", "fp32"):
+        A = A0.clone().requires_grad_(True)
+        b = b0.clone().requires_grad_(True)
+        state = {}
+
+        def fwd():
+            state["x"] = cds.solve_ad(A, b, prec)
+
+        def bwd():
+            A.grad = None
+            b.grad = None
+            (state["x"] * w).sum().backward()
+        tf, _, _ = _events_time(fwd, args.steps, args.warmup)
+        fwd()
+        torch.cuda.synchronize()
+        tb, _, _ = _events_time(lambda: (fwd(), bwd()), args.steps, args.warmup)
+        tb -= tf
+        out[prec] = {"forward_ms": round(tf * 1e3, 3), "backward_ms": round(tb * 1e3, 3),
+                     "forward_gflops": round(batch * 2.0 / 3.0 * n ** 3 / tf / 1e9, 1),
+                     "backward_GBps": round(batch * (8.0 * n * n * 2) / tb / 1e9, 1)}
+        del A, b
+    _line(out)
+
+
+def bench_vbatched(args):
+    """2000 SPD systems, n ~ U{32..1024}, A_i = M M^T / n + I, B_i ~ U[-1,1] n x 4: FP32 Cholesky +
+    FP64 refinement in one persistent launch, largest systems first.  systems/s and the per-system
+    latency (device timestamps, 100 MHz) p50 / p99."""
+    import numpy as np
+    import torch
+    import paper_1511_07174_amd as cds
+    dev = torch.device("cuda", 0)
+    count = 2000
+    rng = np.random.default_rng(30)
+    sizes = rng.integers(32, 1025, size=count)
+    g = torch.Generator(device=dev).manual_seed(30)
+    systems = []
+    for ni in sizes:
+        ni = int(ni)
+        M = torch.rand(ni, ni, generator=g, dtype=torch.float64, device=dev) * 2 - 1
+        A = cds.colmajor(M @ M.T / ni + torch.eye(ni, dtype=torch.float64, device=dev))
+        B = cds.colmajor(torch.rand(ni, 4, generator=g, dtype=torch.float64, device=dev) * 2 - 1)
+        systems.append((A, B))
+    order = np.argsort(-sizes, kind="stable")
+    state = {}
+
+    def run():
+        state["r"] = cds.solve_vbatched(systems, nrhs=4, order=order)
+    t, tmin, tmax = _events_time(run, args.steps, args.warmup)
+    Xs, res, t0, t1 = state["r"]
+    lat = (t1.cpu().numpy() - t0.cpu().numpy()) * 10e-9
+    conv = sum(1 for r in res if r.converged)
+    flops = float(np.sum(sizes.astype(np.float64) ** 3 / 3.0))
+    _line({"metric": "batched uneven SPD systems/s", "workload": "vbatched", "systems": count,
+           "value": round(count / t, 1), "unit": "systems/s", "ms": round(t * 1e3, 3),
+           "ms_min": round(tmin * 1e3, 3), "ms_max": round(tmax * 1e3, 3),
+           "latency_p50_us": round(float(np.percentile(lat, 50)) * 1e6, 1),
+           "latency_p99_us": round(float(np.percentile(lat, 99)) * 1e6, 1),
+           "factor_gflops": round(flops / t / 1e9, 1), "converged": conv,
+           "data": "synthetic, sizes numpy seed 30, matrices device generator seed 30"})
+
+
+def bench_kernels(args):
+    """Per-kernel-class times of getrf + getrs at n = 16384 (FP64 and FP32), from events around every
+    launch on the stream it runs on, with each class's algorithmic rate."""
+    import torch
+    import paper_1511_07174_amd as cds
+    from paper_1511_07174_amd.cds import OPT_KERNEL_TIMING
+    dev = torch.device("cuda", 0)
+    n = args.n
+    g = torch.Generator(device=dev).manual_seed(3)
+    A = cds.colmajor(torch.rand(n, n, generator=g, dtype=torch.float64, device=dev) * 2 - 1)
+    b = torch.rand(n, generator=g, dtype=torch.float64, device=dev) * 2 - 1
+    h = cds.handle()
+    out = {"metric": "kernel classes of getrf + getrs", "workload": "kernels", "n": n}
+    for dt, src in (("fp64", A), ("fp32", A.float())):
+        LU = src.clone()
+        ipiv = torch.zeros(n, dtype=torch.int32, device=dev)
+        info = torch.zeros(1, dtype=torch.int32, device=dev)
+        x = b.to(src.dtype)
+        tc, _, _ = _events_time(lambda: LU.copy_(src), 3, 1)
+        t, _, _ = _events_time(lambda: (LU.copy_(src), h.getrf_(LU, ipiv, info)), args.steps, args.warmup)
+        t -= tc
+        ts, _, _ = _events_time(lambda: h.getrs_(LU, ipiv, x.clone()), args.steps, args.warmup)
+        h.set_option(OPT_KERNEL_TIMING, 1)
+        h.kernel_timing_reset()
+        LU.copy_(src)
+        torch.cuda.synchronize()
+        h.getrf_(LU, ipiv, info)
+        h.getrs_(LU, ipiv, x.clone())
+        torch.cuda.synchronize()
+        cls = {}
+        for kc in ("update", "panel", "laswp", "trsm", "trsv"):
+            cnt, ms, fl, by = h.kernel_timing(kc)
+            cls[kc] = {"launches": cnt, "ms": round(ms, 3), "TFLOPs": round(fl / max(ms, 1e-9) / 1e9, 2),
+                       "GBps": round(by / max(ms, 1e-9) / 1e6, 1)}
+        h.set_option(OPT_KERNEL_TIMING, 0)
+        out[dt] = {"getrf_ms": round(t * 1e3, 3), "getrf_tflops": round(2.0 / 3.0 * n ** 3 / t / 1e12, 2),
+                   "getrs_ms": round(ts * 1e3, 3), "info": int(info.item()), "classes": cls}
+    _line(out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,11 +247,16 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--workload", default="lu", choices=["lu", "chol", "adjoint", "vbatched", "kernels"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the factorization of one "
               "matrix runs on a single MI355X); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "lu":
+        {"chol": bench_chol, "adjoint": bench_adjoint, "vbatched": bench_vbatched,
+         "kernels": bench_kernels}[args.workload](args)
+        return
 
     import numpy as np
     import torch
