@@ -85,7 +85,7 @@ typedef enum {
 typedef enum {
   CDS_TUNE_GETRF_NB = 0,    /* value: block size nb */
   CDS_TUNE_POTRF_NB = 1,    /* value: block size nb */
-  CDS_TUNE_VBATCH_TILE = 2  /* value: inner block of the batched Cholesky for systems of size <= n_max */
+  CDS_TUNE_VBATCH_TILE = 2  /* value: block-column width (32 or 64) of the batched Cholesky for systems of size <= n_max */
 } cds_tune_key_t;
 
 /* Handle: holds the stream, the workspace pointer, options and the tuning

@@ -528,18 +528,21 @@ cds_status_t cds_dposv_mixed_vbatched(cds_handle_t h, cds_prec_t prec, int64_t b
   if (!n || !A || !lda || !B || !ldb || !X || !ldx || !results) return CDS_INVALID_VALUE;
   cds_status_t st = need_ws(h, cds::vbatched_ws_bytes((int)batch, (int)nmax, (int)nrhs));
   if (st != CDS_SUCCESS) return st;
-  int jw16 = 128;
+  // block width per size: systems up to the largest bucket tuned to 32 use 32-wide block columns
+  int jw32 = 256;
   {
     int64_t best = -1;
-    for (const auto& e : h->tune)
-      if (e.key == CDS_TUNE_VBATCH_TILE && e.value == 16 && e.n_max > best) best = e.n_max;
     bool any = false;
-    for (const auto& e : h->tune) any = any || e.key == CDS_TUNE_VBATCH_TILE;
-    if (any) jw16 = (int)std::max<int64_t>(best, 0);
+    for (const auto& e : h->tune) {
+      if (e.key != CDS_TUNE_VBATCH_TILE) continue;
+      any = true;
+      if (e.value == 32 && e.n_max > best) best = e.n_max;
+    }
+    if (any) jw32 = (int)std::min<int64_t>(std::max<int64_t>(best, 0), 1 << 30);
   }
   Ctx c = make_ctx(h);
   return cds::vbatched_run(c, (int)batch, (int)nmax, n, A, lda, B, ldb, X, ldx, (int)nrhs, order, p, results, t_start,
-                           t_end, jw16);
+                           t_end, jw32);
 }
 
 cds_status_t cds_douter_strided_batched(cds_handle_t h, int64_t m, int64_t n, int64_t k, double alpha,

@@ -108,7 +108,7 @@ def tune_potrf(sizes=(2048, 4096, 8192, 16384), dtypes=("f64", "f32"), candidate
 
 
 def tune_vbatched(buckets=((32, 128), (129, 256), (257, 512), (513, 1024)), count=96, seed=0):
-    """For each size bucket, time a batch of systems of that bucket with the 16- and 32-wide block
+    """For each size bucket, time a batch of systems of that bucket with the 32- and 64-wide block
     columns and keep the faster."""
     h = cds.handle()
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -124,7 +124,7 @@ def tune_vbatched(buckets=((32, 128), (129, 256), (257, 512), (513, 1024)), coun
             B = torch.rand(n, 4, generator=g, dtype=torch.float64) * 2 - 1
             systems.append((colmajor(A.to(dev)), colmajor(B.to(dev))))
         best = None
-        for tile in (16, 32):
+        for tile in (32, 64):
             h.tune_clear()
             h.tune_set(cds.TUNE_VBATCH_TILE, cds.R_32F, hi, tile)
             t = _timeit(lambda: solve_vbatched(systems, nrhs=4))
