@@ -161,7 +161,7 @@ def bench_adjoint(args):
 
 def bench_vbatched(args):
     """2000 SPD systems, n ~ U{32..1024}, A_i = M M^T / n + I, B_i ~ U[-1,1] n x 4: FP32 Cholesky +
-    FP64 refinement in one persistent launch, largest systems first.  The descriptors (sizes, pointers,
+    FP64 refinement to eta <= 1e-14 in one persistent launch, largest systems first.  The descriptors (sizes, pointers,
     leading dimensions) are built once; the timed step is the replay of a graph holding the counter
     reset and the persistent launch.  systems/s and the per-system latency (device timestamps,
     100 MHz) p50 / p99."""
@@ -195,10 +195,11 @@ def bench_vbatched(args):
     t1 = torch.zeros(count, dtype=torch.int64, device=dev)
     h = cds.handle()
     nmax = int(sizes.max())
+    prm = cds.default_params(tol=1e-14, success_tol=1e-14)
 
     def call():
         h.posv_mixed_vbatched(count, nmax, ns, Ap, lda, Bp, ldb, Xp, ldx, 4, res, order=order, t_start=t0,
-                              t_end=t1, device=dev)
+                              t_end=t1, params=prm, device=dev)
     te, _, _ = _events_time(call, args.steps, args.warmup)        # eager (also sizes the workspace)
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
@@ -220,7 +221,7 @@ def bench_vbatched(args):
            "latency_p50_us": round(float(np.percentile(lat, 50)) * 1e6, 1),
            "latency_p99_us": round(float(np.percentile(lat, 99)) * 1e6, 1),
            "factor_gflops": round(flops / t / 1e9, 1), "converged": conv,
-           "max_iters": max(r.iters for r in R),
+           "max_iters": max(r.iters for r in R), "max_eta": max(r.eta for r in R), "tol": prm.tol,
            "data": "synthetic, sizes numpy seed 30, matrices device generator seed 30; timed: graph replay"})
 
 

@@ -5,17 +5,17 @@
 //      scratch factor padded with an identity block to a multiple of the block
 //      width JW (32 or 64); each FP64 element of A is read and rounded once, when
 //      its block column is updated.  Per block column, the
-//      rank-j0 delayed update of 64-row chunks runs on MFMA (both operands are
+//      rank-j0 delayed update of 128-row chunks runs on MFMA (both operands are
 //      rows of the row-major factor, read as float4 straight into registers,
 //      several k-slabs in flight), one wave factors the JW x JW diagonal block
 //      in registers and forms its inverse, and the rows below are solved by an
 //      MFMA product with that inverse;
 //   2. solves in FP32 with the stored diagonal-block inverses (the only serial
 //      step per block is one dependent load round trip), and
-//   3. refines with an FP64 residual in which every thread owns whole rows:
-//      the row part of row i reads A(i, 0:i) (coalesced across threads), the
-//      column part reads A(i+1:n, i) (one column per lane), so no cross-lane
-//      reductions and a fixed summation order (graph replays are bitwise equal).
+//   3. refines with an FP64 residual that reads every stored element of A twice,
+//      both times coalesced: once along its row (a thread per row), once along
+//      its column (16 lanes per column); every sum has a fixed order, so graph
+//      replays are bitwise equal.
 // No grid-wide synchronisation, no host interaction: the launch can be captured.
 // The LDS footprint (about 68 KB) leaves room for two workgroups per CU, so the
 // serial diagonal-block and solve phases of one system overlap the MFMA phases
@@ -32,7 +32,6 @@ namespace {
 constexpr int VNT = 256;
 constexpr int VNMAX = 1024;
 constexpr int VNR = 4;      // right-hand sides per pass
-constexpr int CH = 64;      // rows per update chunk
 constexpr int WPAD = 32;    // extra floats per scratch row (spreads rows over channels)
 constexpr int SP = 68;      // LDS row stride (floats) of the chunk and inverse tiles
 constexpr int PD = 3;       // k-slabs (32 wide) in flight in the update
@@ -48,6 +47,7 @@ struct VbArgs {
   float* ws;
   size_t wg_elems;   // floats of scratch per workgroup
   size_t w_elems;    // floats of the factor region (the inverses follow)
+  size_t inv_elems;  // floats of the inverse region (the column sums of the residual follow)
   int* ticket;
   cds_ir_result_t* res;
   uint64_t* t_start; uint64_t* t_end;
@@ -59,7 +59,7 @@ struct VbArgs {
 struct VbShared {
   double xs[VNMAX][VNR];                 // FP64 solution of the current pass
   union {
-    struct { float S[CH][SP]; float Li[64][SP]; float col[64]; } f;      // factorization
+    struct { float S[64][SP]; float Li[64][SP]; float col[64]; float tr[4][16][17]; } f;   // factorization
     struct { float y[VNMAX][VNR]; float part[4096]; float t[64][VNR]; } s;  // solves / residual out
   } u;
   double red[4][2 * VNR + 1];
@@ -71,6 +71,47 @@ struct VbShared {
 __device__ __forceinline__ float lane_read(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
+
+// use(buf, b) for the batches b = 0 .. nb-1, the loads of batch b + 1 in flight while batch b is
+// consumed (two register buffers, ping-pong).
+template <int UN, typename T, typename LoadF, typename UseF>
+__device__ __forceinline__ void pipelined(int nb, LoadF&& load, UseF&& use) {
+  T b0[UN], b1[UN];
+  if (nb > 0) load(b0, 0);
+  for (int b = 0; b < nb; b += 2) {
+    if (b + 1 < nb) load(b1, b + 1);
+    use(b0, b);
+    if (b + 1 >= nb) break;
+    if (b + 2 < nb) load(b0, b + 2);
+    use(b1, b + 1);
+  }
+}
+
+// A flattened software pipeline over work items: `it` starts at the first item,
+// next(it) advances it, valid(it) tells whether it exists; load(buf, it) issues an
+// item's loads, use(buf, it) consumes them.  The next item's loads are in flight
+// while the current one is consumed, across item boundaries.
+template <int UN, typename T, typename Item, typename NextF, typename ValidF, typename LoadF, typename UseF>
+__device__ __forceinline__ void pipelined_items(Item it, NextF&& next, ValidF&& valid, LoadF&& load, UseF&& use) {
+  T b0[UN], b1[UN];
+  if (!valid(it)) return;
+  load(b0, it);
+  while (true) {
+    Item i1 = next(it);
+    const bool v1 = valid(i1);
+    if (v1) load(b1, i1);
+    use(b0, it);
+    if (!v1) break;
+    Item i2 = next(i1);
+    const bool v2 = valid(i2);
+    if (v2) load(b0, i2);
+    use(b1, i1);
+    if (!v2) break;
+    it = i2;
+  }
+}
+
+struct VbItem { int g, b; };
 
 // One wave: factor the JW x JW diagonal block held in S (lower part) in place,
 // L_JJ to S and to Wd (row-major, ld ldw), 1 / L(r, r) to col[], the inverse
@@ -88,7 +129,7 @@ __device__ __attribute__((noinline)) int vb_diag(float* Wd, int ldw, float* Wi, 
   for (int j = 0; j < JW; ++j) {
     const float d = lane_read(v[j], j);
     if (!(d > 0.f)) return j + 1;
-    const float ljj = sqrtf(d), rinv = 1.0f / ljj;
+    const float ljj = sqrtf(d), rinv = __builtin_amdgcn_rsqf(d);   // hardware 1/sqrt (about 1 ulp): the factor is refined in FP64
     v[j] = (r == j) ? ljj : (r > j ? v[j] * rinv : 0.f);
     sh.u.f.col[r] = v[j];
     wave_fence();
@@ -136,26 +177,31 @@ __device__ __attribute__((noinline)) int vb_diag(float* Wd, int ldw, float* Wi, 
 // Left-looking blocked Cholesky of A (n x n, FP64, column-major, lower triangle
 // read), padded with an identity block to np, into W (np x np, FP32, row-major,
 // lower).  Each element of A is read once, when its block column is updated, and
-// rounded to FP32 there.  The inverse of every JW x JW diagonal block goes to
-// Winv (row-major, JW x JW per block).  sh.info = 0, or the 1-based column of the
+// rounded to FP32 there.  Per block column the rows are taken in chunks of 128; a
+// wave owns 32 consecutive rows of the chunk across the whole block column, so each
+// slab of the block's own rows (the second operand) is shared by 128 rows and no
+// wave reads another wave's rows.  The inverse of every JW x JW diagonal block goes
+// to Winv (row-major, JW x JW per block).  sh.info = 0, or the 1-based column of the
 // first non-positive pivot.
 template <int JW>
-__device__ void vb_potrf(const double* A, int64_t lda, int n, float* W, int ldw, float* Winv, int np, VbShared& sh) {
-  constexpr int RT = JW == 64 ? 2 : 1;   // 16-row tiles per wave
-  constexpr int CT = 2;                  // 16-column tiles per wave
+__device__ __attribute__((noinline)) void vb_potrf(const double* A, int64_t lda, int n, float* W, int ldw, float* Winv,
+                                                   int np, VbShared& sh) {
+  constexpr int RT = 2;          // 16-row tiles per wave (32 rows)
+  constexpr int CT = JW / 16;    // 16-column tiles: the whole block column
+  constexpr int CHR = 128;       // rows per chunk
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
-  const int rtb = JW == 64 ? 2 * (wave >> 1) : wave;
-  const int ctb = JW == 64 ? 2 * (wave & 1) : 0;
+  float(*T16)[17] = sh.u.f.tr[wave];
   if (tid == 0) sh.info = 0;
   __syncthreads();
   const int nbJ = np / JW;
   for (int J = 0; J < nbJ; ++J) {
     const int j0 = J * JW;
     const int nsl = j0 / 32;
-    for (int r0 = j0; r0 < np; r0 += CH) {
-      const bool active = r0 + 16 * rtb < np;   // whole row tiles are in or out (np % 32 == 0)
-      // ---- S = A(chunk, block column) - L(chunk, 0:j0) L(block, 0:j0)^T; the A loads are issued
+    for (int r0 = j0; r0 < np; r0 += CHR) {
+      const int wr0 = r0 + 32 * wave;     // this wave's first row
+      const bool active = wr0 < np;       // np % 32 == 0: a wave's 32 rows are all in or all out
+      // ---- S = A(rows, block column) - L(rows, 0:j0) L(block, 0:j0)^T; the A loads are issued
       // first and consumed after the MFMA loop
       double ao[RT][CT][4];
       f4 acc[RT][CT];
@@ -166,7 +212,7 @@ __device__ void vb_potrf(const double* A, int64_t lda, int n, float* W, int ldw,
           acc[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int row = r0 + 16 * (rtb + rt) + 4 * lg + v, col = j0 + 16 * (ctb + ct) + li;
+            const int row = wr0 + 16 * rt + 4 * lg + v, col = j0 + 16 * ct + li;
             ao[rt][ct][v] = (row < n && col < n) ? (row >= col ? A[row + (size_t)col * lda] : 0.0)
                                                  : (row == col ? 1.0 : 0.0);
           }
@@ -175,10 +221,11 @@ __device__ void vb_potrf(const double* A, int64_t lda, int n, float* W, int ldw,
         const float* Ap[RT];
         const float* Bp[CT];
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt) Ap[rt] = W + (size_t)(r0 + 16 * (rtb + rt) + li) * ldw + 4 * lg;
+        for (int rt = 0; rt < RT; ++rt) Ap[rt] = W + (size_t)(wr0 + 16 * rt + li) * ldw + 4 * lg;
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) Bp[ct] = W + (size_t)(j0 + 16 * (ctb + ct) + li) * ldw + 4 * lg;
-        f4 a[PD][RT][2], b[PD][CT][2];
+        for (int ct = 0; ct < CT; ++ct) Bp[ct] = W + (size_t)(j0 + 16 * ct + li) * ldw + 4 * lg;
+        constexpr int PDL = 2;
+        f4 a[PDL][RT][2], b[PDL][CT][2];
         // slab s covers k = 32 s .. 32 s + 31; lane (i, g) holds k = 32 s + 16 h + 4 g + q in a[..][h][q]
         auto load = [&](int p, int s) {
 #pragma unroll
@@ -190,11 +237,11 @@ __device__ void vb_potrf(const double* A, int64_t lda, int n, float* W, int ldw,
           }
         };
 #pragma unroll
-        for (int p = 0; p < PD; ++p)
+        for (int p = 0; p < PDL; ++p)
           if (p < nsl) load(p, p);
-        for (int s0 = 0; s0 < nsl; s0 += PD) {
+        for (int s0 = 0; s0 < nsl; s0 += PDL) {
 #pragma unroll
-          for (int p = 0; p < PD; ++p) {
+          for (int p = 0; p < PDL; ++p) {
             const int s = s0 + p;
             if (s < nsl) {
 #pragma unroll
@@ -207,22 +254,30 @@ __device__ void vb_potrf(const double* A, int64_t lda, int n, float* W, int ldw,
                     for (int ct = 0; ct < CT; ++ct)
                       acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[p][rt][h][q], b[p][ct][h][q],
                                                                          acc[rt][ct], 0, 0, 0);
-              if (s + PD < nsl) load(p, s + PD);
+              if (s + PDL < nsl) load(p, s + PDL);
             }
           }
         }
       }
-      // (MFMA C layout: row 4 g + v, column i of each 16 x 16 tile)
+      // acc <- S (MFMA C layout: row 4 g + v, column i of each 16 x 16 tile)
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            sh.u.f.S[16 * (rtb + rt) + 4 * lg + v][16 * (ctb + ct) + li] = (float)ao[rt][ct][v] - acc[rt][ct][v];
-      __syncthreads();
+          for (int v = 0; v < 4; ++v) acc[rt][ct][v] = (float)ao[rt][ct][v] - acc[rt][ct][v];
+      const int nd = (r0 == j0) ? JW / 32 : 0;   // waves holding rows of the diagonal block
       if (r0 == j0) {
-        // ---- diagonal block: one wave, row r in lane r, right-looking in registers
+        // ---- diagonal block: its rows go to S, one wave factors it and forms the inverse
+        if (wave < nd) {
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+              for (int v = 0; v < 4; ++v) sh.u.f.S[32 * wave + 16 * rt + 4 * lg + v][16 * ct + li] = acc[rt][ct][v];
+        }
+        __syncthreads();
         if (wave == 0) {
           const int fail = vb_diag<JW>(W + (size_t)j0 * ldw + j0, ldw, Winv + (size_t)J * JW * JW, sh);
           if (fail && lane == 0) sh.info = j0 + fail;
@@ -230,30 +285,33 @@ __device__ void vb_potrf(const double* A, int64_t lda, int n, float* W, int ldw,
         __syncthreads();
         if (sh.info != 0) return;
       }
-      // ---- rows below the diagonal block: X = S L_JJ^{-T} (MFMA, operands from LDS)
-      const int rt_lo = (r0 == j0) ? JW / 16 : 0;
-      if (active && rtb >= rt_lo) {
+      // ---- this wave's rows below the diagonal block: X = S L_JJ^{-T} (MFMA; the S tiles go
+      // from the C layout to the operand layout through a per-wave 16 x 16 LDS tile)
+      if (active && wave >= nd) {
         f4 d[RT][CT];
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
           for (int ct = 0; ct < CT; ++ct) d[rt][ct] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kk = 0; kk < JW; kk += 16) {
-          f4 av[RT], bv[CT];
+        for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
-          for (int rt = 0; rt < RT; ++rt)
-            av[rt] = *reinterpret_cast<const f4*>(&sh.u.f.S[16 * (rtb + rt) + li][kk + 4 * lg]);
+          for (int kt = 0; kt < CT; ++kt) {
+            wave_fence();   // the previous tile's reads are done
 #pragma unroll
-          for (int ct = 0; ct < CT; ++ct)
-            bv[ct] = *reinterpret_cast<const f4*>(&sh.u.f.Li[16 * (ctb + ct) + li][kk + 4 * lg]);
+            for (int v = 0; v < 4; ++v) T16[4 * lg + v][li] = acc[rt][kt][v];
+            wave_fence();
+            f4 av;
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
+            for (int q = 0; q < 4; ++q) av[q] = T16[li][4 * lg + q];
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
+            for (int ct = 0; ct < CT; ++ct) {
+              const f4 bv = *reinterpret_cast<const f4*>(&sh.u.f.Li[16 * ct + li][16 * kt + 4 * lg]);
 #pragma unroll
-              for (int ct = 0; ct < CT; ++ct)
-                d[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rt][q], bv[ct][q], d[rt][ct], 0, 0, 0);
+              for (int q = 0; q < 4; ++q)
+                d[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], bv[q], d[rt][ct], 0, 0, 0);
+            }
+          }
         }
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
@@ -261,9 +319,10 @@ __device__ void vb_potrf(const double* A, int64_t lda, int n, float* W, int ldw,
           for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-              W[(size_t)(r0 + 16 * (rtb + rt) + 4 * lg + v) * ldw + j0 + 16 * (ctb + ct) + li] = d[rt][ct][v];
+              W[(size_t)(wr0 + 16 * rt + 4 * lg + v) * ldw + j0 + 16 * ct + li] = d[rt][ct][v];
       }
-      __syncthreads();   // S and the factor stores are complete before the next chunk
+      // the next chunk's S / T16 writes and the factor stores: ordered by the barrier below
+      __syncthreads();
     }
   }
 }
@@ -271,14 +330,14 @@ __device__ void vb_potrf(const double* A, int64_t lda, int n, float* W, int ldw,
 // y <- L^{-T} L^{-1} y (FP32, VNR right-hand sides, y = sh.u.s.y over np rows).
 // L is the row-major factor in W, Winv holds the inverses of its diagonal blocks.
 template <int JW>
-__device__ void vb_potrs(const float* W, int ldw, const float* Winv, int np, VbShared& sh) {
+__device__ __attribute__((noinline)) void vb_potrs(const float* W, int ldw, const float* Winv, int np, VbShared& sh) {
   const int tid = threadIdx.x;
   float(*y)[VNR] = sh.u.s.y;
   float* part = sh.u.s.part;
   float(*t)[VNR] = sh.u.s.t;
   const int nbJ = np / JW;
   constexpr int KP = VNT / JW;   // k partitions of the forward update (4 or 8)
-  constexpr int UN = 4;
+  constexpr int UN = 16;
   // ---- forward: y_J = Linv_J (y_J - L(J, 0:j0) y(0:j0))
   for (int J = 0; J < nbJ; ++J) {
     const int j0 = J * JW;
@@ -291,24 +350,28 @@ __device__ void vb_potrs(const float* W, int ldw, const float* Winv, int np, VbS
       for (int c = 0; c < JW / 4; ++c) lv[c] = *reinterpret_cast<const f4*>(Li + 4 * c);
     }
     f4 acc = {0.f, 0.f, 0.f, 0.f};
-    const float* Lr = W + (size_t)(j0 + i) * ldw;
-    for (int k0 = 4 * p; k0 < j0; k0 += 4 * KP * UN) {
-      f4 lk[UN];
+    const float* Lr = W + (size_t)(j0 + i) * ldw + 4 * p;
+    const int nbt = (j0 + 4 * KP * UN - 1) / (4 * KP * UN);
+    pipelined<UN, f4>(
+        nbt,
+        [&](f4(&lk)[UN], int bt) {
 #pragma unroll
-      for (int u = 0; u < UN; ++u) {
-        const int k = k0 + 4 * KP * u;
-        lk[u] = k < j0 ? *reinterpret_cast<const f4*>(Lr + k) : f4{0.f, 0.f, 0.f, 0.f};
-      }
+          for (int u = 0; u < UN; ++u) {
+            const int k = 4 * p + 4 * KP * (bt * UN + u);
+            lk[u] = k < j0 ? *reinterpret_cast<const f4*>(Lr + 4 * KP * (bt * UN + u)) : f4{0.f, 0.f, 0.f, 0.f};
+          }
+        },
+        [&](f4(&lk)[UN], int bt) {
 #pragma unroll
-      for (int u = 0; u < UN; ++u) {
-        const int k = min(k0 + 4 * KP * u, np - 4);
+          for (int u = 0; u < UN; ++u) {
+            const int k = min(4 * p + 4 * KP * (bt * UN + u), np - 4);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const f4 yk = *reinterpret_cast<const f4*>(y[k + e]);
-          acc += lk[u][e] * yk;
-        }
-      }
-    }
+            for (int e = 0; e < 4; ++e) {
+              const f4 yk = *reinterpret_cast<const f4*>(y[k + e]);
+              acc += lk[u][e] * yk;
+            }
+          }
+        });
     *reinterpret_cast<f4*>(&part[(p * JW + i) * VNR]) = acc;
     __syncthreads();
     if (p < VNR) {
@@ -345,21 +408,26 @@ __device__ void vb_potrs(const float* W, int ldw, const float* Winv, int np, VbS
     f4 acc[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[c] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int r0 = j0 + JW + rp; r0 < np; r0 += RP * UB) {
-      f4 lr[UB];
+    const int nbt = (np - j0 - JW + RP * UB - 1) / (RP * UB);
+    const float* Lc = W + (size_t)(j0 + JW + rp) * ldw + j0 + 4 * cq;
+    pipelined<UB, f4>(
+        nbt,
+        [&](f4(&lr)[UB], int bt) {
 #pragma unroll
-      for (int u = 0; u < UB; ++u) {
-        const int r = r0 + RP * u;
-        lr[u] = r < np ? *reinterpret_cast<const f4*>(W + (size_t)r * ldw + j0 + 4 * cq) : f4{0.f, 0.f, 0.f, 0.f};
-      }
+          for (int u = 0; u < UB; ++u) {
+            const int r = j0 + JW + rp + RP * (bt * UB + u);
+            lr[u] = r < np ? *reinterpret_cast<const f4*>(Lc + (size_t)RP * (bt * UB + u) * ldw) : f4{0.f, 0.f, 0.f, 0.f};
+          }
+        },
+        [&](f4(&lr)[UB], int bt) {
 #pragma unroll
-      for (int u = 0; u < UB; ++u) {
-        const int r = min(r0 + RP * u, np - 1);
-        const f4 xr = *reinterpret_cast<const f4*>(y[r]);
+          for (int u = 0; u < UB; ++u) {
+            const int r = min(j0 + JW + rp + RP * (bt * UB + u), np - 1);
+            const f4 xr = *reinterpret_cast<const f4*>(y[r]);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] += lr[u][c] * xr;
-      }
-    }
+            for (int c = 0; c < 4; ++c) acc[c] += lr[u][c] * xr;
+          }
+        });
 #pragma unroll
     for (int c = 0; c < 4; ++c) *reinterpret_cast<f4*>(&part[(rp * JW + 4 * cq + c) * VNR]) = acc[c];
     __syncthreads();
@@ -379,68 +447,162 @@ __device__ void vb_potrs(const float* W, int ldw, const float* Winv, int np, VbS
   }
 }
 
+// Sum over each 16-lane row of the wave (quad permutes, half-row and row mirrors);
+// every lane of the row gets the row's sum, added in a fixed order.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_move<0xB1>(v);    // quad_perm 1,0,3,2
+  v += dpp_move<0x4E>(v);    // quad_perm 2,3,0,1
+  v += dpp_move<0x141>(v);   // row_half_mirror
+  v += dpp_move<0x140>(v);   // row_mirror
+  return v;
+}
+
 // Residual r = B - A xs in FP64 (A symmetric, lower triangle, column-major); y = fp32(r)
 // (zero on the padding rows).  Returns max_c ||r_c||_inf / (||A||_inf ||x_c||_inf); computes
-// ||A||_inf into sh.anorm when `norm` is set.
-__device__ double vb_residual(const double* A, int64_t lda, const double* B, int64_t ldb, int n, int np, int nr,
-                              bool norm, VbShared& sh) {
+// ||A||_inf into sh.anorm when `norm` is set.  (A xs)_i = sum_{j<=i} A(i,j) x_j + sum_{c>i} A(c,i) x_c:
+//   column part: a wave takes 4 columns at a time, 16 lanes per column walking its rows
+//     (4 x 128 B per load), the 16 partial sums combined inside each 16-lane row; the
+//     per-column sums (4 right-hand sides and sum |A(c,i)|) go to cp (global, this
+//     workgroup's scratch);
+//   row part: thread i walks row i (64 consecutive rows per load) and adds cp[i].
+// Both sweeps run as one software pipeline over all their batches, so the loads of the
+// next column group or row set are in flight while the current one finishes.  Every sum
+// has a fixed order, so the result does not depend on timing.
+__device__ __attribute__((noinline)) double vb_residual(const double* A, int64_t lda, const double* B, int64_t ldb,
+                                                       int n, int np, int nr, bool norm, double* cp, VbShared& sh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr int UN = 8;
-  double rmax[VNR] = {0.0, 0.0, 0.0, 0.0}, xmax[VNR] = {0.0, 0.0, 0.0, 0.0}, amax = 0.0;
-  for (int base = 0; base < np; base += VNT) {
-    const int i = base + tid;
-    const int wlo = base + 64 * wave;                     // first row of this wave
-    const int whi = min(n - 1, wlo + 63);                 // last valid row of this wave
+  constexpr int UN = 16;
+  // ---- column part: items (column group g of 4 columns, batch b of 16 UN rows), g = wave, wave + 4, ...
+  {
+    const int cc = lane >> 4, r = lane & 15;
+    const int ng = (n + 3) / 4;
     double s[VNR] = {0.0, 0.0, 0.0, 0.0}, ab = 0.0;
-    if (wlo < n) {
-      // row part: A(i, 0:i)
-      for (int j0 = 0; j0 <= whi; j0 += UN) {
-        double a[UN];
+    auto nbat = [&](int g) { return (n - 4 * g - 1 + 16 * UN - 1) / (16 * UN); };
+    VbItem first{wave, 0};
+    while (first.g < ng && nbat(first.g) == 0) first.g += 4;   // groups without rows below
+    pipelined_items<UN, double>(
+        first,
+        [&](VbItem t) {
+          if (t.b + 1 < nbat(t.g)) return VbItem{t.g, t.b + 1};
+          int g = t.g + 4;
+          while (g < ng && nbat(g) == 0) g += 4;
+          return VbItem{g, 0};
+        },
+        [&](VbItem t) { return t.g < ng; },
+        [&](double(&a)[UN], VbItem t) {
+          const int i = 4 * t.g + cc;
+          const double* Ac = A + (size_t)min(i, n - 1) * lda;
 #pragma unroll
-        for (int u = 0; u < UN; ++u) {
-          const int j = j0 + u;
-          a[u] = (i < n && j <= i) ? A[i + (size_t)j * lda] : 0.0;
-        }
+          for (int u = 0; u < UN; ++u) {
+            const int c = 4 * t.g + 1 + r + 16 * (t.b * UN + u);
+            a[u] = (i < n && c > i && c < n) ? Ac[c] : 0.0;
+          }
+        },
+        [&](double(&a)[UN], VbItem t) {
 #pragma unroll
-        for (int u = 0; u < UN; ++u) {
-          const int j = min(j0 + u, n - 1);
-          ab += fabs(a[u]);
+          for (int u = 0; u < UN; ++u) {
+            const int c = min(4 * t.g + 1 + r + 16 * (t.b * UN + u), n - 1);
+            ab += fabs(a[u]);
 #pragma unroll
-          for (int q = 0; q < VNR; ++q) s[q] = fma(a[u], sh.xs[j][q], s[q]);
-        }
-      }
-      // column part: A(i+1:n, i), one column per lane
-      const double* Ac = A + (size_t)min(i, n - 1) * lda;
-      for (int c0 = wlo + 1; c0 < n; c0 += UN) {
-        double a[UN];
+            for (int q = 0; q < VNR; ++q) s[q] = fma(a[u], sh.xs[c][q], s[q]);
+          }
+          if (t.b + 1 == nbat(t.g)) {   // last batch of the group: combine the 16 lanes of each column
 #pragma unroll
-        for (int u = 0; u < UN; ++u) {
-          const int c = c0 + u;
-          a[u] = (i < n && c > i && c < n) ? Ac[c] : 0.0;
-        }
+            for (int q = 0; q < VNR; ++q) s[q] = row16_sum(s[q]);
+            ab = row16_sum(ab);
+            const int i = 4 * t.g + cc;
+            if (r == 0 && i < n) {
+              double* o = cp + (size_t)i * 8;
 #pragma unroll
-        for (int u = 0; u < UN; ++u) {
-          const int c = min(c0 + u, n - 1);
-          ab += fabs(a[u]);
+              for (int q = 0; q < VNR; ++q) o[q] = s[q];
+              o[VNR] = ab;
+            }
 #pragma unroll
-          for (int q = 0; q < VNR; ++q) s[q] = fma(a[u], sh.xs[c][q], s[q]);
-        }
+            for (int q = 0; q < VNR; ++q) s[q] = 0.0;
+            ab = 0.0;
+          }
+        });
+    // columns of groups with no rows below (the last column at least) have no column part
+    for (int i = 4 * wave + cc; i < n; i += 16) {
+      if (r == 0 && nbat(i / 4) == 0) {
+        double* o = cp + (size_t)i * 8;
+#pragma unroll
+        for (int q = 0; q <= VNR; ++q) o[q] = 0.0;
       }
     }
-    if (i < np) {
+  }
+  __syncthreads();
+  // ---- row part: items (row set m of 256 rows, batch b of UN columns); thread i = 256 m + tid
+  double rmax[VNR] = {0.0, 0.0, 0.0, 0.0}, xmax[VNR] = {0.0, 0.0, 0.0, 0.0}, amax = 0.0;
+  {
+    const int nm = (np + VNT - 1) / VNT;
+    double s[VNR] = {0.0, 0.0, 0.0, 0.0}, ab = 0.0;
+    // batches of the wave's rows in set m: columns 0 .. min(n - 1, last row of the wave)
+    auto nbat = [&](int m) {
+      const int wlo = VNT * m + 64 * wave;
+      return wlo < n ? (min(n - 1, wlo + 63) + UN) / UN : 0;
+    };
+    auto finish = [&](int m) {
+      const int i = VNT * m + tid;
+      const bool rv = i < n;
+      if (rv) {
+        const double* o = cp + (size_t)i * 8;
 #pragma unroll
-      for (int q = 0; q < VNR; ++q) {
-        float rf = 0.f;
-        if (i < n && q < nr) {
-          const double r = B[i + (size_t)q * ldb] - s[q];
-          rf = (float)r;
-          rmax[q] = fmax(rmax[q], fabs(r));
-          xmax[q] = fmax(xmax[q], fabs(sh.xs[i][q]));
-        }
-        sh.u.s.y[i][q] = rf;
+        for (int q = 0; q < VNR; ++q) s[q] += o[q];
+        ab += o[VNR];
       }
-    }
-    amax = fmax(amax, ab);
+      if (i < np) {
+#pragma unroll
+        for (int q = 0; q < VNR; ++q) {
+          float rf = 0.f;
+          if (rv && q < nr) {
+            const double rr = B[i + (size_t)q * ldb] - s[q];
+            rf = (float)rr;
+            rmax[q] = fmax(rmax[q], fabs(rr));
+            xmax[q] = fmax(xmax[q], fabs(sh.xs[i][q]));
+          }
+          sh.u.s.y[i][q] = rf;
+        }
+      }
+      amax = fmax(amax, ab);
+#pragma unroll
+      for (int q = 0; q < VNR; ++q) s[q] = 0.0;
+      ab = 0.0;
+    };
+    // sets with no valid row of this wave form a suffix: the pipeline stops at the first one
+    pipelined_items<UN, double>(
+        VbItem{0, 0},
+        [&](VbItem t) {
+          if (t.b + 1 < nbat(t.g)) return VbItem{t.g, t.b + 1};
+          return VbItem{t.g + 1, 0};
+        },
+        [&](VbItem t) { return t.g < nm && nbat(t.g) > 0; },
+        [&](double(&a)[UN], VbItem t) {
+          const int i = VNT * t.g + tid;
+#pragma unroll
+          for (int u = 0; u < UN; ++u) {
+            const int j = t.b * UN + u;
+            a[u] = (i < n && j <= i) ? A[i + (size_t)j * lda] : 0.0;
+          }
+        },
+        [&](double(&a)[UN], VbItem t) {
+#pragma unroll
+          for (int u = 0; u < UN; ++u) {
+            const int j = min(t.b * UN + u, n - 1);
+            ab += fabs(a[u]);
+#pragma unroll
+            for (int q = 0; q < VNR; ++q) s[q] = fma(a[u], sh.xs[j][q], s[q]);
+          }
+          if (t.b + 1 == nbat(t.g)) finish(t.g);
+        });
+    for (int m = 0; m < nm; ++m)
+      if (nbat(m) == 0) finish(m);
   }
   // workgroup maxima (exact, order-free)
 #pragma unroll
@@ -472,12 +634,12 @@ __device__ double vb_residual(const double* A, int64_t lda, const double* B, int
       if (!(e <= eta)) eta = e;
     }
   }
-  __syncthreads();   // red[] is reused by the next call
+  __syncthreads();   // red[] and cp are reused by the next call
   return eta;
 }
 
 template <int JW>
-__device__ void vb_system(const VbArgs& a, int sys, float* W, float* Winv, VbShared& sh) {
+__device__ void vb_system(const VbArgs& a, int sys, float* W, float* Winv, double* cp, VbShared& sh) {
   const int tid = threadIdx.x;
   const int n = a.n[sys];
   const int np = (n + JW - 1) / JW * JW;
@@ -519,7 +681,7 @@ __device__ void vb_system(const VbArgs& a, int sys, float* W, float* Winv, VbSha
     int it = 0, reason = 0;
     double eta = 0.0;
     for (it = 0;; ++it) {
-      eta = vb_residual(A, lda, B, ldb, n, np, nr, c0 == 0 && it == 0, sh);
+      eta = vb_residual(A, lda, B, ldb, n, np, nr, c0 == 0 && it == 0, cp, sh);
       if (it == 0 && c0 == 0) first_eta = eta;
       if (!(eta == eta) || eta == INFINITY) reason = 4;
       else if (eta <= a.tol) reason = 1;
@@ -559,6 +721,7 @@ __global__ void __launch_bounds__(VNT, WG_PER_CU) vbatched_kernel(VbArgs a) {
   __shared__ VbShared sh;
   float* W = a.ws + (size_t)blockIdx.x * a.wg_elems;
   float* Winv = W + a.w_elems;
+  double* cp = reinterpret_cast<double*>(Winv + a.inv_elems);
   while (true) {
     if (threadIdx.x == 0) sh.ticket = atomicAdd(a.ticket, 1);
     __syncthreads();
@@ -577,8 +740,8 @@ __global__ void __launch_bounds__(VNT, WG_PER_CU) vbatched_kernel(VbArgs a) {
       }
       continue;
     }
-    if (n <= a.jw32_max_n) vb_system<32>(a, sys, W, Winv, sh);
-    else vb_system<64>(a, sys, W, Winv, sh);
+    if (n <= a.jw32_max_n) vb_system<32>(a, sys, W, Winv, cp, sh);
+    else vb_system<64>(a, sys, W, Winv, cp, sh);
   }
 }
 
@@ -587,7 +750,9 @@ __global__ void reset_kernel(int* p) { *p = 0; }
 int round64(int n) { return (n + 63) / 64 * 64; }
 
 size_t vb_w_elems(int nmax) { return (size_t)round64(nmax) * (round64(nmax) + WPAD); }
-size_t vb_wg_elems(int nmax) { return vb_w_elems(nmax) + (size_t)round64(nmax) * 64; }
+size_t vb_inv_elems(int nmax) { return (size_t)round64(nmax) * 64; }
+// factor, diagonal-block inverses, residual column sums (8 doubles per row)
+size_t vb_wg_elems(int nmax) { return vb_w_elems(nmax) + vb_inv_elems(nmax) + (size_t)round64(nmax) * 16; }
 
 }  // namespace
 
@@ -621,7 +786,7 @@ cds_status_t vbatched_run(Ctx& c, int batch, int nmax, const int32_t* n, const d
   VbArgs a;
   a.batch = batch; a.nrhs = nrhs;
   a.n = n; a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.X = X; a.ldx = ldx; a.order = order;
-  a.ws = ws; a.wg_elems = vb_wg_elems(nmax); a.w_elems = vb_w_elems(nmax);
+  a.ws = ws; a.wg_elems = vb_wg_elems(nmax); a.w_elems = vb_w_elems(nmax); a.inv_elems = vb_inv_elems(nmax);
   a.ticket = ticket; a.res = res; a.t_start = t_start; a.t_end = t_end;
   a.tol = prm.tol; a.success_tol = prm.success_tol; a.max_iter = prm.max_iter;
   a.jw32_max_n = jw32_max_n;
