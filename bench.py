@@ -109,6 +109,19 @@ def bench_chol(args):
     tm, _, _ = _events_time(lambda: h.posv_mixed(A, b, X, Llo, res, precision="fp32", params=prm), args.steps,
                             args.warmup)
     r = decode_results(res)[0]
+    # per-class times of one FP64 potrf (events around every launch)
+    from paper_1511_07174_amd.cds import OPT_KERNEL_TIMING
+    h.set_option(OPT_KERNEL_TIMING, 1)
+    h.kernel_timing_reset()
+    L.copy_(A)
+    torch.cuda.synchronize()
+    h.potrf_(L, info)
+    torch.cuda.synchronize()
+    cls = {}
+    for kc, name in (("update", "syrk"), ("panel", "potf2"), ("trsm", "trsm")):
+        cnt, ms, fl, by = h.kernel_timing(kc)
+        cls[name] = {"launches": cnt, "ms": round(ms, 3), "TFLOPs": round(fl / max(ms, 1e-9) / 1e9, 2)}
+    h.set_option(OPT_KERNEL_TIMING, 0)
     oracle.build()
     Ah = np.asfortranarray(A.cpu().numpy())
     bh = b.cpu().numpy()
@@ -119,7 +132,7 @@ def bench_chol(args):
            "potrf_frac_of_f64_peak": round(n ** 3 / 3 / t / 78.6e12, 4), "potrs_ms": round(ts * 1e3, 3),
            "potrs_GBps": round(8.0 * n * n / ts / 1e9, 1), "fp64_eta": eta64,
            "posv_fp32_ir_ms": round(tm * 1e3, 3), "posv_ir_iters": r.iters, "posv_eta": eta_mixed,
-           "posv_converged": bool(r.converged), "data": "synthetic, device generator seed 6"})
+           "posv_converged": bool(r.converged), "classes": cls, "data": "synthetic, device generator seed 6"})
 
 
 def bench_adjoint(args):

@@ -1,9 +1,10 @@
 // Blocked right-looking Cholesky A = L L^T (Sec. 2: "In the case of SPD
 // matrices, we have A = LL^t"), lower triangle only.
-//   potf2_kernel   one workgroup factors the jb x jb diagonal block in 32-wide
-//                  sub-blocks; the first non-positive (or NaN) pivot records
-//                  info and stops the factorization (every later kernel of the
-//                  call sees info != 0 and returns).
+//   potf2_lds_kernel / potf2_kernel   one workgroup factors the jb x jb
+//                  diagonal block in 32-wide sub-blocks (held in LDS for jb <= 128);
+//                  the first non-positive (or NaN) pivot records info and stops the
+//                  factorization (every later kernel of the call sees info != 0 and
+//                  returns).
 // L21 = A21 L11^{-T} is the MFMA triangular solve of trsm.hip on the transposed
 // rows; the trailing update A22 -= L21 L21^T is the MFMA GEMM in lower-tile mode.
 #include "common.hpp"
@@ -103,6 +104,141 @@ __global__ void __launch_bounds__(256) potf2_kernel(T* A, int64_t lda, int k, in
   }
 }
 
+
+template <typename T>
+__device__ __forceinline__ T lane_get(T v, int l) {
+  if constexpr (std::is_same<T, double>::value) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l), hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+  } else {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+  }
+}
+
+// jb <= 128: the whole diagonal block lives in LDS (column-major, ld 129) for the
+// duration of the kernel; it is read from and written to global memory once.  Per
+// 32-wide sub-block: (a) one wave factors the sub-block's diagonal with row r in
+// lane r (registers), column j broadcast through LDS, division by L(j,j) so that
+// exact data stays exact; (b) the rows below in the block are solved against it,
+// one row per thread; (c) the rest of the block gets the symmetric rank-32 update
+// in 4 x 4 register tiles.
+constexpr int PJB = 128, PLD = PJB + 1;
+
+template <typename T>
+__global__ void __launch_bounds__(256) potf2_lds_kernel(T* A, int64_t lda, int k, int jb, int32_t* info) {
+  __shared__ T Ds[PJB * PLD];   // (r, c) at Ds[c * PLD + r]
+  __shared__ T colb[64];
+  __shared__ int s_fail;
+  if (*info != 0) return;
+  T* D = A + k + (size_t)k * lda;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int idx = tid; idx < jb * jb; idx += 256) {
+    const int r = idx % jb, c = idx / jb;
+    Ds[c * PLD + r] = r >= c ? D[r + (size_t)c * lda] : (T)0;
+  }
+  if (tid == 0) s_fail = 0;
+  __syncthreads();
+  for (int s0 = 0; s0 < jb; s0 += SB) {
+    const int sw = min(SB, jb - s0);
+    // (a) the sub-block's diagonal
+    if (wave == 0) {
+      const int r = lane;
+      // rows sw .. SB-1 of a short last sub-block are padded with the identity, so every
+      // step runs (straight-line code; after a failed pivot the rest is not used)
+      T v[SB];
+#pragma unroll
+      for (int c = 0; c < SB; ++c)
+        v[c] = r < sw ? (c <= r && c < sw ? Ds[(s0 + c) * PLD + s0 + r] : (T)0) : (c == r ? (T)1 : (T)0);
+      int fail = 0;
+#pragma unroll
+      for (int j = 0; j < SB; ++j) {
+        const T d = lane_get(v[j], j);   // a_jj minus the updates of the previous columns
+        if (fail == 0 && !(d > (T)0)) fail = j + 1;
+        const T ljj = sqrt_t(d);
+        v[j] = (r == j) ? ljj : (r > j ? v[j] / ljj : (T)0);
+        colb[r] = v[j];
+        wave_fence();
+#pragma unroll
+        for (int c = j + 1; c < SB; ++c) v[c] -= v[j] * colb[c];
+        wave_fence();
+      }
+      if (fail) {
+        if (lane == 0) {
+          s_fail = 1;
+          atomicCAS(info, 0, k + s0 + fail);
+        }
+      } else if (r < sw) {
+#pragma unroll
+        for (int c = 0; c < SB; ++c)
+          if (c <= r) Ds[(s0 + c) * PLD + s0 + r] = v[c];
+      }
+    }
+    __syncthreads();
+    if (s_fail) break;
+    // (b) rows below the sub-block: x L11^T = a
+    const int rem = jb - s0 - sw;
+    for (int t = tid; t < rem; t += 256) {
+      const int i = s0 + sw + t;
+      T x[SB];
+#pragma unroll
+      for (int c = 0; c < SB; ++c) x[c] = c < sw ? Ds[(s0 + c) * PLD + i] : (T)0;
+#pragma unroll
+      for (int c = 0; c < SB; ++c) {
+        if (c < sw) {
+          T vv = x[c];
+#pragma unroll
+          for (int u = 0; u < c; ++u) vv -= x[u] * Ds[(s0 + u) * PLD + s0 + c];
+          x[c] = vv / Ds[(s0 + c) * PLD + s0 + c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < SB; ++c)
+        if (c < sw) Ds[(s0 + c) * PLD + i] = x[c];
+    }
+    __syncthreads();
+    // (c) trailing part of the block: 4 x 4 tiles (ti >= tc) of the lower triangle
+    const int b0 = s0 + sw, nt = (rem + 3) / 4, ntiles = nt * (nt + 1) / 2;
+    for (int tile = tid; tile < ntiles; tile += 256) {
+      int ti = (int)((sqrtf(8.0f * tile + 1.0f) - 1.0f) * 0.5f);
+      while (ti * (ti + 1) / 2 > tile) --ti;
+      while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+      const int tc = tile - ti * (ti + 1) / 2;
+      const int i0 = b0 + 4 * ti, c0 = b0 + 4 * tc;
+      T acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
+      for (int u = 0; u < sw; ++u) {
+        const T* P = Ds + (s0 + u) * PLD;
+        T pi[4], pc[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          pi[a] = i0 + a < jb ? P[i0 + a] : (T)0;
+          pc[a] = c0 + a < jb ? P[c0 + a] : (T)0;
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] += pi[a] * pc[b];
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int i = i0 + a, c = c0 + b;
+          if (i < jb && c <= i) Ds[c * PLD + i] -= acc[a][b];
+        }
+    }
+    __syncthreads();
+  }
+  // the factored (or, after a failed pivot, partially factored) lower triangle back to A
+  for (int idx = tid; idx < jb * jb; idx += 256) {
+    const int r = idx % jb, c = idx / jb;
+    if (r >= c) D[r + (size_t)c * lda] = Ds[c * PLD + r];
+  }
+}
+
 }  // namespace
 
 size_t potrf_ws_bytes(int n, int nb, size_t elem) {
@@ -119,42 +255,64 @@ cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int
   if (n == 0) return CDS_SUCCESS;
   if (nb <= 0) nb = n <= 2048 ? 128 : 256;
   nb = std::min(512, std::max(SB, (nb / SB) * SB));
-  for (int k = 0; k < n; k += nb) {
-    const int jb = std::min(nb, n - k);
-    size_t psm = sizeof(T) * (size_t)(SB + 1) * (SB + jb);
+  double* linv = (double*)((char*)c.ws + kErrRegion);
+  // the diagonal block of block column k, L21 below it, and (mode 2) the operand scale
+  auto panel = [&](int k, int jb, hipStream_t st) -> cds_status_t {
     {
-      KScope ks(c.timer, CDS_KC_PANEL, s, (double)jb * jb * jb / 3.0, (double)jb * jb * sizeof(T));
-      hipLaunchKernelGGL((potf2_kernel<T>), dim3(1), dim3(256), psm, s, A, lda, k, jb, info);
+      KScope ks(c.timer, CDS_KC_PANEL, st, (double)jb * jb * jb / 3.0, (double)jb * jb * sizeof(T));
+      if (jb <= PJB) {
+        hipLaunchKernelGGL((potf2_lds_kernel<T>), dim3(1), dim3(256), 0, st, A, lda, k, jb, info);
+      } else {
+        const size_t psm = sizeof(T) * (size_t)(SB + 1) * (SB + jb);
+        hipLaunchKernelGGL((potf2_kernel<T>), dim3(1), dim3(256), psm, st, A, lda, k, jb, info);
+      }
     }
     if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
     const int rem = n - k - jb;
-    if (rem <= 0) break;
+    if (rem <= 0) return CDS_SUCCESS;
     {
       // L21 = A21 L11^{-T}: the transposed column solve L11 L21^T = A21^T on MFMA tiles
-      KScope ks(c.timer, CDS_KC_TRSM, s, (double)jb * jb * rem, 0.0);
-      double* linv = (double*)((char*)c.ws + kErrRegion);
-      if (launch_diag_inv16<T>(A + k + (size_t)k * lda, lda, 0, jb, 0, linv, 0, 1, s) != hipSuccess)
+      KScope ks(c.timer, CDS_KC_TRSM, st, (double)jb * jb * rem, 0.0);
+      if (launch_diag_inv16<T>(A + k + (size_t)k * lda, lda, 0, jb, 0, linv, 0, 1, st) != hipSuccess)
         return CDS_HIP_ERROR;
       if (launch_trsm16<T>(A + k + (size_t)k * lda, lda, 0, linv, 0, A + (k + jb) + (size_t)k * lda, lda, 0, jb, rem,
-                           1, 1, info, s) != hipSuccess)
+                           1, 1, info, st) != hipSuccess)
         return CDS_HIP_ERROR;
     }
-    GemmArgs<T> g;
-    g.m = rem; g.n = rem; g.k = jb;
-    g.A = A + (k + jb) + (size_t)k * lda; g.lda = lda; g.strideA = 0;
-    g.B = A + (k + jb) + (size_t)k * lda; g.ldb = lda; g.strideB = 0;
-    g.C = A + (k + jb) + (size_t)(k + jb) * lda; g.ldc = lda; g.strideC = 0;
-    g.alpha = (T)-1; g.transB = 1; g.lower = 1; g.scale_exp = nullptr;
-    g.guard = info;
     if (mode == 2 && scale_exp != nullptr) {
       if constexpr (std::is_same<T, float>::value) {
-        if (launch_maxabs_exp(A + (k + jb) + (size_t)k * lda, lda, 0, rem, jb, scale_exp, 1, s) != hipSuccess)
+        if (launch_maxabs_exp(A + (k + jb) + (size_t)k * lda, lda, 0, rem, jb, scale_exp, 1, st) != hipSuccess)
           return CDS_HIP_ERROR;
       }
-      g.scale_exp = scale_exp;
     }
-    KScope ks(c.timer, CDS_KC_UPDATE, s, (double)rem * (rem + 1) * jb, (double)sizeof(T) * ((double)rem * (rem + 1) + (double)rem * jb));
-    if (launch_gemm<T>(g, 1, mode, s) != hipSuccess) return CDS_HIP_ERROR;
+    return CDS_SUCCESS;
+  };
+  // A[r0:n, c0:c1] -= L21(r0:n) L21(c0:c1)^T, lower tiles only (L21 = A[k+jb:n, k:k+jb])
+  auto update = [&](int k, int jb, int r0, int c0, int c1, hipStream_t st) -> cds_status_t {
+    const int m = n - r0, nn = c1 - c0;
+    if (m <= 0 || nn <= 0) return CDS_SUCCESS;
+    GemmArgs<T> g;
+    g.m = m; g.n = nn; g.k = jb;
+    g.A = A + r0 + (size_t)k * lda; g.lda = lda; g.strideA = 0;
+    g.B = A + c0 + (size_t)k * lda; g.ldb = lda; g.strideB = 0;
+    g.C = A + r0 + (size_t)c0 * lda; g.ldc = lda; g.strideC = 0;
+    g.alpha = (T)-1; g.transB = 1; g.lower = 1; g.scale_exp = nullptr;
+    g.guard = info;
+    if (mode == 2 && scale_exp != nullptr) g.scale_exp = scale_exp;
+    KScope ks(c.timer, CDS_KC_UPDATE, st, (double)m * nn * jb * 2.0 - (double)nn * nn * jb,
+              (double)sizeof(T) * ((double)m * nn + (double)(m + nn) * jb));
+    return launch_gemm<T>(g, 1, mode, st) == hipSuccess ? CDS_SUCCESS : CDS_HIP_ERROR;
+  };
+  // Right-looking, in stream order.  (A two-stream look-ahead, as in getrf, measured slower here: the
+  // trailing update keeps two workgroups on every CU, so the one-workgroup diagonal-block kernel
+  // only starts when the update drains and the extra next-column launch is pure overhead.)
+  for (int k = 0; k < n; k += nb) {
+    const int jb = std::min(nb, n - k);
+    cds_status_t st = panel(k, jb, s);
+    if (st != CDS_SUCCESS) return st;
+    if (n - k - jb <= 0) break;
+    st = update(k, jb, k + jb, k + jb, n, s);
+    if (st != CDS_SUCCESS) return st;
   }
   return CDS_SUCCESS;
 }
