@@ -278,6 +278,39 @@ def bench_kernels(args):
     _line(out)
 
 
+def bench_copy(args):
+    """A plain 1 GiB device-to-device copy (reads 1 GiB, writes 1 GiB): the HBM reference for the
+    rooflines, and the kernel whose FETCH_SIZE / WRITE_SIZE counters calibrate the traffic figures."""
+    import torch
+    dev = torch.device("cuda", 0)
+    x = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    y = torch.empty_like(x)
+    t, tmin, _ = _events_time(lambda: y.copy_(x), args.steps, args.warmup)
+    nbytes = 2.0 * x.numel() * 4
+    _line({"metric": "device copy GB/s (read + write)", "workload": "copy", "bytes": nbytes,
+           "ms": round(t * 1e3, 3), "GBps": round(nbytes / t / 1e9, 1), "GBps_best": round(nbytes / tmin / 1e9, 1)})
+
+
+def traffic_for(kernel_key):
+    """HBM bytes per launch of a kernel from the committed counter summary (profiles/traffic.json),
+    or None when the kernel's source changed since the counters were taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            tab = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = tab.get(kernel_key)
+    if not e:
+        return None
+    with open(os.path.join(here, e["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != e["source_sha256"]:
+            return None
+    return e["bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -288,7 +321,7 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", default="lu", choices=["lu", "chol", "adjoint", "vbatched", "kernels"])
+    ap.add_argument("--workload", default="lu", choices=["lu", "chol", "adjoint", "vbatched", "kernels", "copy"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the factorization of one "
@@ -296,7 +329,7 @@ def main():
         sys.exit(2)
     if args.workload != "lu":
         {"chol": bench_chol, "adjoint": bench_adjoint, "vbatched": bench_vbatched,
-         "kernels": bench_kernels}[args.workload](args)
+         "kernels": bench_kernels, "copy": bench_copy}[args.workload](args)
         return
 
     import numpy as np
@@ -409,7 +442,8 @@ def main():
         "fp64": fp64,
         "speedup_vs_fp64": round(fp64["ms"] / (t_mixed * 1e3), 3) if fp64 else None,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2) if achieved else None, "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4) if achieved else None, "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4) if achieved else None,
+                     "traffic": traffic_for("update_%s_n%d" % (args.precision, n)),
                      "kernel": "trailing update (%s MFMA), %d launches/step, avg %.1f us" %
                                (args.precision, cnt // max(1, args.steps), upd_avg_ms * 1e3)},
         "panel": {"launches_per_step": pan[0] // max(1, args.steps),
