@@ -316,6 +316,22 @@ __device__ __forceinline__ int ceil_div(int a, int b) { return (a + b - 1) / b; 
 // Orders LDS accesses between the lanes of one wave (lanes run in lockstep and
 // the LDS serves one wave's requests in order; this keeps the compiler from
 // moving accesses across the point).
+// Sum over each 16-lane row of the wave (quad permutes, half-row and row mirrors);
+// every lane of the row gets the row's sum, added in a fixed order.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_move<0xB1>(v);    // quad_perm 1,0,3,2
+  v += dpp_move<0x4E>(v);    // quad_perm 2,3,0,1
+  v += dpp_move<0x141>(v);   // row_half_mirror
+  v += dpp_move<0x140>(v);   // row_mirror
+  return v;
+}
+
 __device__ __forceinline__ void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();

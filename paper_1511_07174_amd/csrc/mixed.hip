@@ -356,6 +356,69 @@ __global__ void __launch_bounds__(256) convert_sym_kernel(const double* A, int64
   }
 }
 
+// Symmetric A held in its lower triangle: (A x)_r = sum_{j<=r} A(r,j) x_j + sum_{i>r} A(i,r) x_i.
+// Row part over one column chunk (thread per row, 64 consecutive rows per load): part[chunk][r].
+__global__ void __launch_bounds__(256) residual_sym_row_kernel(const double* A, int64_t lda, const double* X,
+                                                               int64_t ldx, int n, int c, int chunk, double* part,
+                                                               const int* active) {
+  if (active && active[0] == 0) return;
+  const double* x = X + (size_t)c * ldx;
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int j0 = blockIdx.y * chunk;
+  const int rmax = min(n - 1, (int)blockIdx.x * 256 + 255);
+  const int j1 = min(min(n, j0 + chunk), rmax + 1);   // nothing of the chunk above the block's last row
+  double s0 = 0.0, s1 = 0.0;
+  if (r < n) {
+    int j = j0;
+    for (; j + 8 <= j1; j += 8) {
+      double a[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) a[t] = (j + t <= r) ? A[r + (size_t)(j + t) * lda] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 8; t += 2) {
+        s0 = fma(a[t], x[j + t], s0);
+        s1 = fma(a[t + 1], x[j + t + 1], s1);
+      }
+    }
+    for (; j < j1; ++j)
+      if (j <= r) s0 = fma(A[r + (size_t)j * lda], x[j], s0);
+    part[(size_t)blockIdx.y * n + r] = s0 + s1;
+  }
+}
+
+// Column part: sum_{i>r} A(i,r) x_i for 16 columns per workgroup, 4 per wave, 16 lanes per column
+// (each load reads 4 x 128 B), combined inside each 16-lane row: out[r].
+__global__ void __launch_bounds__(256) residual_sym_col_kernel(const double* A, int64_t lda, const double* X,
+                                                               int64_t ldx, int n, int c, double* out,
+                                                               const int* active) {
+  if (active && active[0] == 0) return;
+  const double* x = X + (size_t)c * ldx;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cc = lane >> 4, rl = lane & 15;
+  const int g0 = blockIdx.x * 16 + wave * 4;      // this wave's first column
+  const int col = g0 + cc;
+  const double* Ac = A + (size_t)min(col, n - 1) * lda;
+  constexpr int UN = 8;
+  double s0 = 0.0, s1 = 0.0;
+  for (int i0 = g0 + 1 + rl; i0 < n; i0 += 16 * UN) {
+    double a[UN], xv[UN];
+#pragma unroll
+    for (int u = 0; u < UN; ++u) {
+      const int i = i0 + 16 * u;
+      const bool ok = col < n && i > col && i < n;
+      a[u] = ok ? Ac[i] : 0.0;
+      xv[u] = ok ? x[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UN; u += 2) {
+      s0 = fma(a[u], xv[u], s0);
+      s1 = fma(a[u + 1], xv[u + 1], s1);
+    }
+  }
+  const double s = row16_sum(s0 + s1);
+  if (rl == 0 && col < n) out[col] = s;
+}
+
 // R = B - A X for symmetric A held in its lower triangle (same split as above).
 __global__ void __launch_bounds__(256) residual_sym_kernel(const double* A, int64_t lda, const double* X, int64_t ldx,
                                                            const double* B, int64_t ldb, double* R, int64_t ldr,
@@ -539,6 +602,20 @@ static cds_status_t refine(Ctx& c, const IrWs& w, int trans, int chol, int n, in
       hipLaunchKernelGGL(residual_kernel, dim3(rblocks, batch), dim3(256), 0, s, A, lda, strideA, (const double*)X,
                          ldx, strideX, B, ldb, strideB, w.R, (int64_t)n, (int64_t)n * nrhs, n, nrhs, trans, w.rnorm,
                          w.xnorm, (const int*)w.active);
+    } else if (batch == 1) {
+      // symmetric: row parts over column chunks, the column part in the last slot, then the fixed-order sum
+      const int rb256 = (n + 255) / 256;
+      const int nchunk = std::max(1, std::min(kResChunks - 1, 1024 / std::max(1, rb256)));
+      const int chunk = (n + nchunk - 1) / nchunk;
+      for (int cc = 0; cc < nrhs; ++cc) {
+        hipLaunchKernelGGL(residual_sym_row_kernel, dim3(rb256, nchunk), dim3(256), 0, s, A, lda, (const double*)X, ldx,
+                           n, cc, chunk, w.part, (const int*)w.active);
+        hipLaunchKernelGGL(residual_sym_col_kernel, dim3((n + 15) / 16), dim3(256), 0, s, A, lda, (const double*)X, ldx,
+                           n, cc, w.part + (size_t)nchunk * n, (const int*)w.active);
+        hipLaunchKernelGGL(residual_finish_kernel, dim3(rb256, 1), dim3(256), 0, s, (const double*)X, ldx, (int64_t)0,
+                           B, ldb, (int64_t)0, w.R, (int64_t)n, (int64_t)n * nrhs, n, cc, nrhs, nchunk + 1,
+                           (const double*)w.part, w.rnorm, w.xnorm, (const int*)w.active);
+      }
     } else {
       hipLaunchKernelGGL(residual_sym_kernel, dim3(rblocks), dim3(256), 0, s, A, lda, (const double*)X, ldx, B, ldb,
                          w.R, (int64_t)n, n, nrhs, w.rnorm, w.xnorm, (const int*)w.active);

@@ -447,22 +447,6 @@ __device__ __attribute__((noinline)) void vb_potrs(const float* W, int ldw, cons
   }
 }
 
-// Sum over each 16-lane row of the wave (quad permutes, half-row and row mirrors);
-// every lane of the row gets the row's sum, added in a fixed order.
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-__device__ __forceinline__ double row16_sum(double v) {
-  v += dpp_move<0xB1>(v);    // quad_perm 1,0,3,2
-  v += dpp_move<0x4E>(v);    // quad_perm 2,3,0,1
-  v += dpp_move<0x141>(v);   // row_half_mirror
-  v += dpp_move<0x140>(v);   // row_mirror
-  return v;
-}
-
 // Residual r = B - A xs in FP64 (A symmetric, lower triangle, column-major); y = fp32(r)
 // (zero on the padding rows).  Returns max_c ||r_c||_inf / (||A||_inf ||x_c||_inf); computes
 // ||A||_inf into sh.anorm when `norm` is set.  (A xs)_i = sum_{j<=i} A(i,j) x_j + sum_{c>i} A(c,i) x_c:
