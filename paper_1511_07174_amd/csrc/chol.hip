@@ -120,21 +120,32 @@ __device__ __forceinline__ T lane_get(T v, int l) {
 // 32-wide sub-block: (a) one wave factors the sub-block's diagonal with row r in
 // lane r (registers), column j broadcast through LDS, division by L(j,j) so that
 // exact data stays exact; (b) the rows below in the block are solved against it,
-// one row per thread; (c) the rest of the block gets the symmetric rank-32 update
-// in 4 x 4 register tiles.
+// one row per thread, with the reciprocal of the diagonal; (c) the rest of the
+// block gets the symmetric rank-32 update on MFMA tiles.
 constexpr int PJB = 128, PLD = PJB + 1;
 
 template <typename T>
 __global__ void __launch_bounds__(256) potf2_lds_kernel(T* A, int64_t lda, int k, int jb, int32_t* info) {
   __shared__ T Ds[PJB * PLD];   // (r, c) at Ds[c * PLD + r]
   __shared__ T colb[64];
+  __shared__ T rdiag[SB];
   __shared__ int s_fail;
   if (*info != 0) return;
   T* D = A + k + (size_t)k * lda;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int idx = tid; idx < jb * jb; idx += 256) {
-    const int r = idx % jb, c = idx / jb;
-    Ds[c * PLD + r] = r >= c ? D[r + (size_t)c * lda] : (T)0;
+  // 16 loads in flight per thread (the block is jb x jb, at most 64 elements per thread)
+  for (int base = 0; base < jb * jb; base += 16 * 256) {
+    T v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = base + u * 256 + tid, r = idx % jb, c = idx / jb;
+      v[u] = (idx < jb * jb && r >= c) ? D[r + (size_t)c * lda] : (T)0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int idx = base + u * 256 + tid;
+      if (idx < jb * jb) Ds[(idx / jb) * PLD + idx % jb] = v[u];
+    }
   }
   if (tid == 0) s_fail = 0;
   __syncthreads();
@@ -171,11 +182,16 @@ __global__ void __launch_bounds__(256) potf2_lds_kernel(T* A, int64_t lda, int k
 #pragma unroll
         for (int c = 0; c < SB; ++c)
           if (c <= r) Ds[(s0 + c) * PLD + s0 + r] = v[c];
+        T vr = (T)1;
+#pragma unroll
+        for (int c = 0; c < SB; ++c) vr = (c == r) ? v[c] : vr;
+        rdiag[r] = (T)1 / vr;
       }
     }
     __syncthreads();
     if (s_fail) break;
-    // (b) rows below the sub-block: x L11^T = a
+    // (b) rows below the sub-block: x L11^T = a; the dot products in four independent partial
+    // sums, the diagonal applied as a precomputed reciprocal (no division on the chain)
     const int rem = jb - s0 - sw;
     for (int t = tid; t < rem; t += 256) {
       const int i = s0 + sw + t;
@@ -185,10 +201,17 @@ __global__ void __launch_bounds__(256) potf2_lds_kernel(T* A, int64_t lda, int k
 #pragma unroll
       for (int c = 0; c < SB; ++c) {
         if (c < sw) {
-          T vv = x[c];
+          T p0 = (T)0, p1 = (T)0, p2 = (T)0, p3 = (T)0;
 #pragma unroll
-          for (int u = 0; u < c; ++u) vv -= x[u] * Ds[(s0 + u) * PLD + s0 + c];
-          x[c] = vv / Ds[(s0 + c) * PLD + s0 + c];
+          for (int u = 0; u + 3 < c; u += 4) {
+            p0 += x[u] * Ds[(s0 + u) * PLD + s0 + c];
+            p1 += x[u + 1] * Ds[(s0 + u + 1) * PLD + s0 + c];
+            p2 += x[u + 2] * Ds[(s0 + u + 2) * PLD + s0 + c];
+            p3 += x[u + 3] * Ds[(s0 + u + 3) * PLD + s0 + c];
+          }
+#pragma unroll
+          for (int u = c & ~3; u < c; ++u) p0 += x[u] * Ds[(s0 + u) * PLD + s0 + c];
+          x[c] = (x[c] - ((p0 + p1) + (p2 + p3))) * rdiag[c];
         }
       }
 #pragma unroll
@@ -196,39 +219,38 @@ __global__ void __launch_bounds__(256) potf2_lds_kernel(T* A, int64_t lda, int k
         if (c < sw) Ds[(s0 + c) * PLD + i] = x[c];
     }
     __syncthreads();
-    // (c) trailing part of the block: 4 x 4 tiles (ti >= tc) of the lower triangle
-    const int b0 = s0 + sw, nt = (rem + 3) / 4, ntiles = nt * (nt + 1) / 2;
-    for (int tile = tid; tile < ntiles; tile += 256) {
-      int ti = (int)((sqrtf(8.0f * tile + 1.0f) - 1.0f) * 0.5f);
-      while (ti * (ti + 1) / 2 > tile) --ti;
-      while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
-      const int tc = tile - ti * (ti + 1) / 2;
-      const int i0 = b0 + 4 * ti, c0 = b0 + 4 * tc;
-      T acc[4][4];
+    // (c) trailing part of the block on MFMA: 16 x 16 tiles (ti >= tc) of the lower triangle, one
+    // tile per wave at a time, D = P_rows P_cols^T with P = the sub-block's columns below it
+    {
+      constexpr bool F64 = std::is_same<T, double>::value;
+      typedef typename std::conditional<F64, d4, f4>::type acc_t;
+      const int b0 = s0 + sw, nt = (rem + 15) / 16, ntiles = nt * (nt + 1) / 2;
+      const int li = lane & 15, lg = lane >> 4;
+      for (int tile = wave; tile < ntiles; tile += 4) {
+        int ti = (int)((sqrtf(8.0f * tile + 1.0f) - 1.0f) * 0.5f);
+        while (ti * (ti + 1) / 2 > tile) --ti;
+        while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+        const int tc = tile - ti * (ti + 1) / 2;
+        const int i0 = b0 + 16 * ti, c0 = b0 + 16 * tc;
+        acc_t acc;
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+        for (int v = 0; v < 4; ++v) acc[v] = (T)0;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
-      for (int u = 0; u < sw; ++u) {
-        const T* P = Ds + (s0 + u) * PLD;
-        T pi[4], pc[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          pi[a] = i0 + a < jb ? P[i0 + a] : (T)0;
-          pc[a] = c0 + a < jb ? P[c0 + a] : (T)0;
+        for (int k4 = 0; k4 < SB; k4 += 4) {
+          const int kk = k4 + lg;
+          const T a = (kk < sw && i0 + li < jb) ? Ds[(s0 + kk) * PLD + i0 + li] : (T)0;
+          const T b = (kk < sw && c0 + li < jb) ? Ds[(s0 + kk) * PLD + c0 + li] : (T)0;
+          if constexpr (F64)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+          else
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
         }
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] += pi[a] * pc[b];
+        for (int v = 0; v < 4; ++v) {
+          const int i = i0 + (F64 ? (lg + 4 * v) : (4 * lg + v)), c = c0 + li;
+          if (i < jb && c <= i) Ds[c * PLD + i] -= acc[v];
+        }
       }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int i = i0 + a, c = c0 + b;
-          if (i < jb && c <= i) Ds[c * PLD + i] -= acc[a][b];
-        }
     }
     __syncthreads();
   }
