@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(256) rownorm_kernel(const double* A0, int64_t 
 }
 
 // R = B - op(A) X (FP64).  op N: 64 rows per workgroup, waves split the columns.
-// op T: row i of A^T is column i of A: one wave per output, lanes split the sum.
+// op T: row i of A^T is column i of A: 16 lanes per output, four outputs per wave.
 __global__ void __launch_bounds__(256) residual_kernel(const double* A0, int64_t lda, int64_t strideA,
                                                        const double* X0, int64_t ldx, int64_t strideX,
                                                        const double* B0, int64_t ldb, int64_t strideB, double* R0,
@@ -110,23 +110,38 @@ __global__ void __launch_bounds__(256) residual_kernel(const double* A0, int64_t
       }
       __syncthreads();
     } else {
-      // 64 outputs per workgroup, 16 per wave
-      double mloc = 0.0, xloc = 0.0;
-      for (int o = 0; o < 16; ++o) {
-        const int i = blockIdx.x * 64 + wave * 16 + o;
-        if (i >= n) break;
-        double s = 0.0;
-        const double* col = A + (size_t)i * lda;
-        for (int j = lane; j < n; j += 64) s = fma(col[j], x[j], s);
-        s = wave_sum(s);
-        const double rv = B[i + (size_t)c * ldb] - s;
-        if (lane == 0) R[i + (size_t)c * ldr] = rv;
-        mloc = fmax(mloc, fabs(rv));
-        xloc = fmax(xloc, fabs(x[i]));
+      // op T: 16 outputs (columns of A) per workgroup, 4 per wave, 16 lanes per column walking its
+      // rows (4 x 128 B per load, 8 loads in flight per lane), combined inside each 16-lane row
+      const int cc = lane >> 4, rl = lane & 15;
+      const int i = blockIdx.x * 16 + wave * 4 + cc;
+      const double* col = A + (size_t)min(i, n - 1) * lda;
+      double s0 = 0.0, s1 = 0.0;
+      for (int j0 = rl; j0 < n; j0 += 16 * 8) {
+        double a[8], xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int j = j0 + 16 * u;
+          const bool ok = i < n && j < n;
+          a[u] = ok ? col[j] : 0.0;
+          xv[u] = ok ? x[j] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+          s0 = fma(a[u], xv[u], s0);
+          s1 = fma(a[u + 1], xv[u + 1], s1);
+        }
       }
+      const double sum = row16_sum(s0 + s1);
+      double rv = 0.0, xi = 0.0;
+      if (rl == 0 && i < n) {
+        rv = B[i + (size_t)c * ldb] - sum;
+        R[i + (size_t)c * ldr] = rv;
+        xi = x[i];
+      }
+      const double m = wave_max(fabs(rv)), xm = wave_max(fabs(xi));
       if (lane == 0) {
-        atomic_max_nonneg(rnorm + (size_t)b * nrhs + c, mloc);
-        atomic_max_nonneg(xnorm + (size_t)b * nrhs + c, xloc);
+        atomic_max_nonneg(rnorm + (size_t)b * nrhs + c, m);
+        atomic_max_nonneg(xnorm + (size_t)b * nrhs + c, xm);
       }
     }
   }
@@ -599,7 +614,7 @@ static cds_status_t refine(Ctx& c, const IrWs& w, int trans, int chol, int n, in
                            (const double*)w.part, w.rnorm, w.xnorm, (const int*)w.active);
       }
     } else if (!chol) {
-      hipLaunchKernelGGL(residual_kernel, dim3(rblocks, batch), dim3(256), 0, s, A, lda, strideA, (const double*)X,
+      hipLaunchKernelGGL(residual_kernel, dim3(trans ? (n + 15) / 16 : rblocks, batch), dim3(256), 0, s, A, lda, strideA, (const double*)X,
                          ldx, strideX, B, ldb, strideB, w.R, (int64_t)n, (int64_t)n * nrhs, n, nrhs, trans, w.rnorm,
                          w.xnorm, (const int*)w.active);
     } else if (batch == 1) {
@@ -683,7 +698,7 @@ static cds_status_t fallback_fp64(Ctx& c, const IrWs& w, int chol, int trans, in
     if (launch_fill_zero(w.rnorm, (size_t)nrhs * 8, s) != hipSuccess) return CDS_HIP_ERROR;
     if (launch_fill_zero(w.xnorm, (size_t)nrhs * 8, s) != hipSuccess) return CDS_HIP_ERROR;
     if (!chol) {
-      hipLaunchKernelGGL(residual_kernel, dim3((n + 63) / 64, 1), dim3(256), 0, s, A + (size_t)b * strideA, lda,
+      hipLaunchKernelGGL(residual_kernel, dim3(trans ? (n + 15) / 16 : (n + 63) / 64, 1), dim3(256), 0, s, A + (size_t)b * strideA, lda,
                          (int64_t)0, (const double*)(X + (size_t)b * strideX), ldx, (int64_t)0,
                          B + (size_t)b * strideB, ldb, (int64_t)0, w.R, (int64_t)n, (int64_t)0, n, nrhs, trans,
                          w.rnorm, w.xnorm, (const int*)nullptr);
