@@ -271,7 +271,7 @@ cds_status_t cds_tune_set(cds_handle_t h, cds_tune_key_t key, cds_dtype_t dtype,
   if (key < CDS_TUNE_GETRF_NB || key > CDS_TUNE_VBATCH_TILE) return CDS_INVALID_VALUE;
   if (dtype != CDS_R_64F && dtype != CDS_R_32F) return CDS_INVALID_VALUE;
   if (n_max < 0 || value <= 0 || value > 512) return CDS_INVALID_VALUE;
-  if (key == CDS_TUNE_VBATCH_TILE && value != 16 && value != 32) return CDS_INVALID_VALUE;
+  if (key == CDS_TUNE_VBATCH_TILE && value != 32 && value != 64) return CDS_INVALID_VALUE;
   for (auto& e : h->tune)
     if (e.key == key && e.dtype == dtype && e.n_max == n_max) { e.value = value; return CDS_SUCCESS; }
   h->tune.push_back(TuneEntry{key, dtype, n_max, value});

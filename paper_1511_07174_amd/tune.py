@@ -107,32 +107,51 @@ def tune_potrf(sizes=(2048, 4096, 8192, 16384), dtypes=("f64", "f32"), candidate
     return entries, timings
 
 
-def tune_vbatched(buckets=((32, 128), (129, 256), (257, 512), (513, 1024)), count=96, seed=0):
-    """For each size bucket, time a batch of systems of that bucket with the 32- and 64-wide block
-    columns and keep the faster."""
+def tune_vbatched(count=2000, nmax=1024, seed=7, thresholds=(0, 128, 256, 512, 1024)):
+    """The batched SPD kernel takes 32-wide block columns for systems up to a threshold and 64-wide ones
+    above it.  Time one mixed batch (count systems, n ~ U{32..nmax}, largest first) for each threshold
+    and keep the fastest: the workgroups of one launch share the chip, so a bucket timed alone does
+    not predict the mix."""
+    import numpy as np
     h = cds.handle()
     dev = torch.device("cuda", torch.cuda.current_device())
-    g = torch.Generator(device="cpu").manual_seed(seed)
-    entries, timings = [], []
-    from .solvers import solve_vbatched
-    for lo, hi in buckets:
-        systems = []
-        for _ in range(count):
-            n = int(torch.randint(lo, hi + 1, (1,), generator=g))
-            M = torch.rand(n, n, generator=g, dtype=torch.float64) * 2 - 1
-            A = M @ M.T / n + torch.eye(n, dtype=torch.float64)
-            B = torch.rand(n, 4, generator=g, dtype=torch.float64) * 2 - 1
-            systems.append((colmajor(A.to(dev)), colmajor(B.to(dev))))
-        best = None
-        for tile in (32, 64):
-            h.tune_clear()
-            h.tune_set(cds.TUNE_VBATCH_TILE, cds.R_32F, hi, tile)
-            t = _timeit(lambda: solve_vbatched(systems, nrhs=4))
-            timings.append({"bucket": [lo, hi], "tile": tile, "ms": t * 1e3})
-            if best is None or t < best[1]:
-                best = (tile, t)
-        entries.append({"key": "vbatch_tile", "dtype": "f32", "n_max": hi, "value": best[0]})
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(32, nmax + 1, size=count)
+    g = torch.Generator(device=dev).manual_seed(seed)
+    systems = []
+    for n in sizes:
+        n = int(n)
+        M = torch.rand(n, n, generator=g, dtype=torch.float64, device=dev) * 2 - 1
+        A = M @ M.T / n + torch.eye(n, dtype=torch.float64, device=dev)
+        B = torch.rand(n, 4, generator=g, dtype=torch.float64, device=dev) * 2 - 1
+        systems.append((colmajor(A), colmajor(B)))
+    # descriptors built once: only the launch is timed
+    ordt = torch.as_tensor(np.argsort(-sizes, kind="stable"), dtype=torch.int32, device=dev)
+    ns = torch.tensor([a.shape[0] for a, _ in systems], dtype=torch.int32, device=dev)
+    Ap = torch.tensor([a.data_ptr() for a, _ in systems], dtype=torch.int64, device=dev)
+    lda = torch.tensor([a.stride(1) for a, _ in systems], dtype=torch.int64, device=dev)
+    Bp = torch.tensor([b.data_ptr() for _, b in systems], dtype=torch.int64, device=dev)
+    ldb = torch.tensor([b.stride(1) for _, b in systems], dtype=torch.int64, device=dev)
+    Xs = [colmajor(torch.zeros_like(b)) for _, b in systems]
+    Xp = torch.tensor([x.data_ptr() for x in Xs], dtype=torch.int64, device=dev)
+    ldx = torch.tensor([x.stride(1) for x in Xs], dtype=torch.int64, device=dev)
+    res = torch.zeros(count * cds.IR_RESULT_BYTES, dtype=torch.uint8, device=dev)
+    prm = cds.default_params(tol=1e-14, success_tol=1e-14)
+    timings = []
+    best = None
+    for t in thresholds:
+        h.tune_clear()
+        h.tune_set(cds.TUNE_VBATCH_TILE, cds.R_32F, max(t, 1), 32 if t > 0 else 64)
+        ms = _timeit(lambda: h.posv_mixed_vbatched(count, nmax, ns, Ap, lda, Bp, ldb, Xp, ldx, 4, res, order=ordt,
+                                                   params=prm, device=dev), reps=3) * 1e3
+        timings.append({"vbatch_width32_max_n": t, "systems": count, "ms": ms})
+        if best is None or ms < best[1]:
+            best = (t, ms)
     h.tune_clear()
+    t = best[0]
+    entries = [{"key": "vbatch_tile", "dtype": "f32", "n_max": t, "value": 32}] if t > 0 else []
+    if t < nmax:
+        entries.append({"key": "vbatch_tile", "dtype": "f32", "n_max": nmax, "value": 64})
     return entries, timings
 
 

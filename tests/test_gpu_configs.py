@@ -2,6 +2,8 @@
 size, the Householder kappa sweep with every factorization precision, the
 batched differentiable solve, and the uneven-size SPD batch (including
 capture into a graph and replay)."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -161,6 +163,38 @@ def test_vbatched_largest_first(cds):
         assert oracle.eta_inf(A, host(X), B) <= 1e-14
         assert a1 > a0 > 0
     assert cds.handle().device_error() == 0
+
+
+@pytest.mark.parametrize("width", [32, 64])
+def test_vbatched_block_widths(cds, width):
+    """Both block-column widths of the batched Cholesky, forced through the tuning table, on sizes that
+    are below, at and just above multiples of 32 and 64 (identity padding), plus nrhs = 5 (two passes)."""
+    from paper_1511_07174_amd import tune
+    from paper_1511_07174_amd.cds import TUNE_VBATCH_TILE, R_32F
+    sizes = [1, 2, 31, 32, 33, 63, 64, 65, 100, 127, 128, 129, 255, 257, 383, 511, 640]
+    g = synth.rng(41)
+    host_sys, dev_sys = [], []
+    for n in sizes:
+        M = g.uniform(-1, 1, (n, n))
+        A = M @ M.T / n + np.eye(n)
+        B = g.uniform(-1, 1, (n, 5))
+        host_sys.append((A, B))
+        dev_sys.append((to_dev(A), to_dev(B)))
+    h = cds.handle()
+    try:
+        h.tune_clear()
+        h.tune_set(TUNE_VBATCH_TILE, R_32F, 1024, width)
+        Xs, res, t0, t1 = cds.solve_vbatched(dev_sys, nrhs=5)
+    finally:
+        path = tune.default_table_path()
+        if os.path.exists(path):
+            tune.load_table(path, h)
+        else:
+            h.tune_clear()
+    for (A, B), X, r in zip(host_sys, Xs, res):
+        assert r.info == 0 and r.converged, (A.shape[0], r)
+        assert oracle.eta_inf(A, host(X), B) <= 1e-14
+    assert h.device_error() == 0
 
 
 def test_vbatched_graph_replay(cds):
