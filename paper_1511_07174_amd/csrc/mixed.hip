@@ -36,10 +36,17 @@ __global__ void __launch_bounds__(256) convert_kernel(const double* A0, int64_t 
   __shared__ double part[4][64];
   double s = 0.0;
   if (r < n) {
-    for (int j = wave; j < n; j += 4) {
-      const double v = A[r + (size_t)j * lda];
-      Bf[r + (size_t)j * ldb] = (float)v;
-      s += fabs(v);
+    // 8 columns per step and wave (32 per workgroup step): 8 loads in flight per lane
+    for (int j0 = wave; j0 < n; j0 += 32) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = j0 + 4 * u < n ? A[r + (size_t)(j0 + 4 * u) * lda] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (j0 + 4 * u < n) {
+          Bf[r + (size_t)(j0 + 4 * u) * ldb] = (float)v[u];
+          s += fabs(v[u]);
+        }
     }
   }
   part[wave][lane] = s;
@@ -339,33 +346,58 @@ __global__ void __launch_bounds__(256) colnorm_kernel(const double* A0, int64_t 
 // Symmetric matrix held in its lower triangle: row r of A is A(r, 0..r) followed by
 // A(r+1.., r) (column r below the diagonal).  Converts the lower triangle to FP32
 // (the strict upper triangle of the copy is not written) and computes ||A||_inf.
+// Column part of the symmetric row sums: colabs[i] = sum_{c>i} |A(c,i)| (16 lanes per column, 4 columns
+// per wave, 8 loads in flight per lane, combined inside each 16-lane row).
+__global__ void __launch_bounds__(256) sym_colabs_kernel(const double* A, int64_t lda, int n, double* colabs) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cc = lane >> 4, rl = lane & 15;
+  const int g0 = blockIdx.x * 16 + wave * 4;
+  const int col = g0 + cc;
+  const double* Ac = A + (size_t)min(col, n - 1) * lda;
+  double s0 = 0.0, s1 = 0.0;
+  for (int i0 = g0 + 1 + rl; i0 < n; i0 += 16 * 8) {
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + 16 * u;
+      a[u] = (col < n && i > col && i < n) ? Ac[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u += 2) {
+      s0 += fabs(a[u]);
+      s1 += fabs(a[u + 1]);
+    }
+  }
+  const double t = row16_sum(s0 + s1);
+  if (rl == 0 && col < n) colabs[col] = t;
+}
+
+// Lower triangle of A to FP32 (row part of the symmetric row sums on the way) and ||A||_inf with the
+// column parts from sym_colabs_kernel.
 __global__ void __launch_bounds__(256) convert_sym_kernel(const double* A, int64_t lda, float* Bf, int64_t ldb, int n,
-                                                          double* anorm) {
+                                                          const double* colabs, double* anorm) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = blockIdx.x * 64 + lane;
   __shared__ double part[4][64];
-  __shared__ double colp[64];
   double s = 0.0;
   if (r < n) {
-    for (int j = wave; j <= r; j += 4) {
-      const double v = A[r + (size_t)j * lda];
-      Bf[r + (size_t)j * ldb] = (float)v;
-      s += fabs(v);
+    const int jmax = min(n - 1, (int)blockIdx.x * 64 + 63);   // the block's last row
+    for (int j0 = wave; j0 <= jmax; j0 += 32) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = j0 + 4 * u <= r ? A[r + (size_t)(j0 + 4 * u) * lda] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (j0 + 4 * u <= r) {
+          Bf[r + (size_t)(j0 + 4 * u) * ldb] = (float)v[u];
+          s += fabs(v[u]);
+        }
     }
   }
   part[wave][lane] = s;
-  for (int o = 0; o < 16; ++o) {
-    const int loc = wave * 16 + o;
-    const int rr = blockIdx.x * 64 + loc;
-    double t = 0.0;
-    if (rr < n)
-      for (int i = rr + 1 + lane; i < n; i += 64) t += fabs(A[i + (size_t)rr * lda]);
-    t = wave_sum(t);
-    if (lane == 0) colp[loc] = t;
-  }
   __syncthreads();
   if (wave == 0) {
-    double t = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane] + colp[lane];
+    double t = ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) + (r < n ? colabs[r] : 0.0);
     t = wave_max(t);
     if (lane == 0) atomic_max_nonneg(anorm, t);
   }
@@ -772,7 +804,10 @@ cds_status_t posv_mixed_run(Ctx& c, int prec, int n, int nrhs, const double* A, 
   if (!carve(c.ws, c.ws_bytes, n, nrhs, 1, prm.fallback, w)) return CDS_WORKSPACE_TOO_SMALL;
   if (launch_fill_zero(w.anorm, 8, s) != hipSuccess) return CDS_HIP_ERROR;
   // lower triangle to FP32 and the norm of the symmetric matrix
-  hipLaunchKernelGGL(convert_sym_kernel, dim3((n + 63) / 64, 1), dim3(256), 0, s, A, lda, L, (int64_t)n, n, w.anorm);
+  hipLaunchKernelGGL(sym_colabs_kernel, dim3((n + 15) / 16), dim3(256), 0, s, A, lda, n, w.part);
+  if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
+  hipLaunchKernelGGL(convert_sym_kernel, dim3((n + 63) / 64, 1), dim3(256), 0, s, A, lda, L, (int64_t)n, n,
+                     (const double*)w.part, w.anorm);
   if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
   Ctx ci = c;
   ci.ws = w.inner; ci.ws_bytes = w.inner_bytes;
