@@ -247,7 +247,8 @@ cds_status_t cds_dposv_mixed(cds_handle_t handle, cds_prec_t prec, cds_fill_t fi
  * Many SPD systems of uneven size in one persistent launch: FP32 Cholesky and
  * FP32 triangular solves inside one workgroup per system, FP64 refinement.
  * Systems are taken largest-first from a device ticket counter.  All arrays
- * are device arrays of length batch.  n[i] in [1, nmax]; A[i] (n x n, lda[i]);
+ * are device arrays of length batch.  n[i] in [1, nmax] (a system outside it is
+ * skipped with results[i].info = -1, nothing of it read); A[i] (n x n, lda[i]);
  * B[i], X[i] (n x nrhs, ldb[i] / ldx[i]).  results[i] as above.  t_start[i] /
  * t_end[i] (may be NULL): device wall-clock ticks (100 MHz) when the system's
  * work started / ended.  order (may be NULL): processing order (a permutation

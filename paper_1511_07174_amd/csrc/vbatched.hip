@@ -38,7 +38,7 @@ constexpr int PD = 3;       // k-slabs (32 wide) in flight in the update
 constexpr int WG_PER_CU = 2;
 
 struct VbArgs {
-  int batch, nrhs;
+  int batch, nrhs, nmax;
   const int32_t* n;
   const double* const* A; const int64_t* lda;
   const double* const* B; const int64_t* ldb;
@@ -715,7 +715,7 @@ __global__ void __launch_bounds__(VNT, WG_PER_CU) vbatched_kernel(VbArgs a) {
     const int sys = a.order ? a.order[t] : t;
     if (sys < 0 || sys >= a.batch) continue;
     const int n = a.n[sys];
-    if (n < 1 || n > VNMAX || (size_t)((n + 63) / 64 * 64) * ((n + 63) / 64 * 64 + WPAD) > a.w_elems) {
+    if (n < 1 || n > a.nmax || n > VNMAX) {
       // invalid size: report and skip (no memory outside the scratch matrix is touched)
       if (threadIdx.x == 0) {
         cds_ir_result_t* r = a.res + sys;
@@ -768,7 +768,7 @@ cds_status_t vbatched_run(Ctx& c, int batch, int nmax, const int32_t* n, const d
   hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(1), 0, c.s0, ticket);
   if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
   VbArgs a;
-  a.batch = batch; a.nrhs = nrhs;
+  a.batch = batch; a.nrhs = nrhs; a.nmax = nmax;
   a.n = n; a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.X = X; a.ldx = ldx; a.order = order;
   a.ws = ws; a.wg_elems = vb_wg_elems(nmax); a.w_elems = vb_w_elems(nmax); a.inv_elems = vb_inv_elems(nmax);
   a.ticket = ticket; a.res = res; a.t_start = t_start; a.t_end = t_end;
