@@ -55,6 +55,82 @@ struct SlotLayout {
   __host__ __device__ int64_t sw(int par, int e) const { return 2 * cs_par() + par * sw_par() + (int64_t)e * jb * LLW; }
 };
 
+// Gather half of a column step for up to 64 workgroups (one-word values).
+// Lane i polls workgroup i's header, and lane l < wl word l of row j.  Each
+// poll round also fetches, with one coalesced load, the candidate row of the
+// best header seen so far.  The loop ends when every header and row j are in
+// and the row held is that of the final best.  If the last header to arrive
+// does not change the best, the pivot row is then already in registers and
+// costs no round trip of its own.  Same outputs as colstep_exchange.
+template <typename T, int W>
+__device__ __forceinline__ void colstep_gather_fast(const uint64_t* slots, const SlotLayout<T, W>& L, int m, int wl,
+                                                    int cc, int j, int par, uint32_t flag, T* prow, T* prm, T* jrow,
+                                                    int* s_p, int* err) {
+  static_assert(LLWords<T>::n == 1, "one word per value");
+  const int lane = lane_id();
+  const bool hv = lane < L.G;
+  const uint64_t* hp = slots + L.hdr(par, hv ? lane : 0);
+  const uint64_t* jp = slots + L.rowj(par) + (lane < wl ? lane : 0);
+  bool h_ok = !hv, j_ok = lane >= wl, r_ok = true;
+  T hm = (T)-1;
+  int hr = 0x7fffffff;
+  uint32_t jv = 0u, rv = 0u;
+  int row_of = -1;   // workgroup whose candidate row rv holds (wave-uniform)
+  T bm;
+  int br;
+  long long spins = 0;
+  while (true) {
+    wave_pivot_search<T>(hm, hr, h_ok, bm, br);
+    const int bw = bm >= (T)0 ? br / PNT : -1;
+    if (bw != row_of) {
+      row_of = bw;
+      r_ok = lane >= wl || bw < 0;
+    }
+    if (__all(h_ok && j_ok && r_ok)) break;
+    uint64_t hw0 = 0, hw1 = 0, rw = 0, jw = 0;
+    if (!h_ok) {
+      hw0 = __hip_atomic_load(const_cast<uint64_t*>(hp), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      hw1 = __hip_atomic_load(const_cast<uint64_t*>(hp + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!r_ok)
+      rw = __hip_atomic_load(const_cast<uint64_t*>(slots + L.cand(par, row_of) + lane), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    if (!j_ok) jw = __hip_atomic_load(const_cast<uint64_t*>(jp), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!h_ok && (uint32_t)(hw0 >> 32) == flag && (uint32_t)(hw1 >> 32) == flag) {
+      h_ok = true;
+      hm = __uint_as_float((uint32_t)hw0);
+      hr = (int)(uint32_t)hw1;
+    }
+    if (!r_ok && (uint32_t)(rw >> 32) == flag) {
+      r_ok = true;
+      rv = (uint32_t)rw;
+    }
+    if (!j_ok && (uint32_t)(jw >> 32) == flag) {
+      j_ok = true;
+      jv = (uint32_t)jw;
+    }
+    ++spins;
+    if ((spins & 1023) == 0) {
+      const bool stop =
+          __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 || spins > (kSpinLimit >> 2);
+      if (stop) {
+        if (spins > (kSpinLimit >> 2)) atomicExch(err, (int)kErrSpinTimeout);
+        break;
+      }
+    }
+  }
+  // a column without any comparable candidate (NaN entries) keeps row j, taken from row j's message
+  const int p = (br >= j && br < m) ? br : j;
+  const bool from_cand = p == br;
+  if (lane < W) {
+    const T x = lane < wl ? __uint_as_float(from_cand ? rv : jv) : (T)0;
+    prow[lane] = x;
+    prm[lane] = lane > cc ? x : (T)0;
+    if (p != j) jrow[lane] = lane < wl ? __uint_as_float(jv) : (T)0;
+  }
+  if (lane == 0) *s_p = p;
+}
+
 // Column-step exchange, executed by wave 0 of every panel workgroup: this
 // workgroup's best candidate (from the per-wave results) is published with its
 // row, then every workgroup's header is read and the global pivot agreed on.
@@ -85,9 +161,17 @@ __device__ __forceinline__ void colstep_exchange(uint64_t* slots, const SlotLayo
     ll_store_val(hdr, mag, flag);
     ll_store(hdr + LLW, (uint32_t)row, flag);
   }
-  if (mag >= (T)0 && lane < wl)
-    ll_store_val(slots + L.cand(par, g) + lane * LLW, rowbuf[(row - g * PNT) >> 6][lane], flag);
+  // the candidate row goes out even without a candidate (zeros), so a reader may poll it unconditionally
+  if (lane < wl)
+    ll_store_val(slots + L.cand(par, g) + lane * LLW, mag >= (T)0 ? rowbuf[(row - g * PNT) >> 6][lane] : (T)0,
+                 flag);
   if (j / PNT == g && lane < wl) ll_store_val(slots + L.rowj(par) + lane * LLW, jbuf[lane], flag);
+  if constexpr (LLW == 1) {
+    if (L.G <= kWave) {
+      colstep_gather_fast<T, W>(slots, L, m, wl, cc, j, par, flag, prow, prm, jrow, s_p, err);
+      return;
+    }
+  }
   // every workgroup's header (one combined wait per header)
   T bm = (T)-1;
   int br = 0x7fffffff;
