@@ -192,11 +192,25 @@ gemm_native_kernel(GemmArgs<T> g) {
   // the read overlaps the prologue) and alpha is applied to the staged A
   // operand (exact for alpha = -1), which leaves a store-only epilogue.
   typedef typename std::conditional<std::is_same<T, double>::value, d4, f4>::type acc_t;
+  // FP32: a lane's four accumulators of a 16 x 16 block are four consecutive rows of one
+  // column, so C moves as one 16-byte access per block wherever the group is whole and aligned
+  constexpr bool CV4 = std::is_same<T, float>::value;
+  const bool c_al = CV4 && ((uintptr_t)C % 16 == 0) && (g.ldc % 4 == 0);
+  auto c_group = [&](int mi, int ni, int& gi0, int& gj) {
+    gi0 = row0 + wr + mi * 16 + 4 * (lane / 16);
+    gj = col0 + wc + ni * 16 + (lane & 15);
+    return c_al && gi0 + 3 < g.m && gj < g.n && (!g.lower || gi0 >= gj);
+  };
   acc_t acc[4][4];
 #pragma unroll
   for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 4; ++ni)
+    for (int ni = 0; ni < 4; ++ni) {
+      int gi0, gj0;
+      if (c_group(mi, ni, gi0, gj0)) {
+        if constexpr (CV4) acc[mi][ni] = *reinterpret_cast<const f4*>(C + gi0 + (size_t)gj0 * g.ldc);
+        continue;
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = std::is_same<T, double>::value ? (lane / 16 + 4 * v) : (4 * (lane / 16) + v);
@@ -204,6 +218,7 @@ gemm_native_kernel(GemmArgs<T> g) {
         const int gj = col0 + wc + ni * 16 + (lane & 15);
         acc[mi][ni][v] = (gi < g.m && gj < g.n && (!g.lower || gi >= gj)) ? C[gi + (size_t)gj * g.ldc] : (T)0;
       }
+    }
 
   const int ktiles = (g.k + BK - 1) / BK;
   load_tile(0);
@@ -255,7 +270,12 @@ gemm_native_kernel(GemmArgs<T> g) {
 #pragma unroll
   for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 4; ++ni)
+    for (int ni = 0; ni < 4; ++ni) {
+      int gi0, gj0;
+      if (c_group(mi, ni, gi0, gj0)) {
+        if constexpr (CV4) *reinterpret_cast<f4*>(C + gi0 + (size_t)gj0 * g.ldc) = acc[mi][ni];
+        continue;
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         int r = std::is_same<T, double>::value ? (lane / 16 + 4 * v) : (4 * (lane / 16) + v);
@@ -263,6 +283,7 @@ gemm_native_kernel(GemmArgs<T> g) {
         int gj = col0 + wc + ni * 16 + (lane & 15);
         if (gi < g.m && gj < g.n && (!g.lower || gi >= gj)) C[gi + (size_t)gj * g.ldc] = acc[mi][ni][v];
       }
+    }
 }
 
 // ------------------------------------------------------------------------------------
