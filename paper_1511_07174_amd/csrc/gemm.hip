@@ -201,6 +201,18 @@ gemm_native_kernel(GemmArgs<T> g) {
     gj = col0 + wc + ni * 16 + (lane & 15);
     return c_al && gi0 + 3 < g.m && gj < g.n && (!g.lower || gi0 >= gj);
   };
+  // element (gi, gj) of C held in accumulator v of block (mi, ni): FP32 keeps the MFMA layout
+  // (row 4 (lane / 16) + v, column lane & 15); FP64 computes the transposed block, so its
+  // rows are lane & 15 (16 lanes cover 16 consecutive rows) and its columns lane / 16 + 4 v
+  auto acc_pos = [&](int mi, int ni, int v, int& gi, int& gj) {
+    if constexpr (std::is_same<T, double>::value) {
+      gi = row0 + wr + mi * 16 + (lane & 15);
+      gj = col0 + wc + ni * 16 + lane / 16 + 4 * v;
+    } else {
+      gi = row0 + wr + mi * 16 + 4 * (lane / 16) + v;
+      gj = col0 + wc + ni * 16 + (lane & 15);
+    }
+  };
   acc_t acc[4][4];
 #pragma unroll
   for (int mi = 0; mi < 4; ++mi)
@@ -213,9 +225,8 @@ gemm_native_kernel(GemmArgs<T> g) {
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = std::is_same<T, double>::value ? (lane / 16 + 4 * v) : (4 * (lane / 16) + v);
-        const int gi = row0 + wr + mi * 16 + r;
-        const int gj = col0 + wc + ni * 16 + (lane & 15);
+        int gi, gj;
+        acc_pos(mi, ni, v, gi, gj);
         acc[mi][ni][v] = (gi < g.m && gj < g.n && (!g.lower || gi >= gj)) ? C[gi + (size_t)gj * g.ldc] : (T)0;
       }
     }
@@ -246,8 +257,9 @@ gemm_native_kernel(GemmArgs<T> g) {
       for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni) {
+          // FP64 forms the transposed block (operands swapped): lane & 15 then runs down the rows of C
           if constexpr (std::is_same<T, double>::value)
-            acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[cur][mi], bf[cur][ni], acc[mi][ni], 0, 0, 0);
+            acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[cur][ni], af[cur][mi], acc[mi][ni], 0, 0, 0);
           else
             acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[cur][mi], bf[cur][ni], acc[mi][ni], 0, 0, 0);
         }
@@ -278,9 +290,8 @@ gemm_native_kernel(GemmArgs<T> g) {
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int r = std::is_same<T, double>::value ? (lane / 16 + 4 * v) : (4 * (lane / 16) + v);
-        int gi = row0 + wr + mi * 16 + r;
-        int gj = col0 + wc + ni * 16 + (lane & 15);
+        int gi, gj;
+        acc_pos(mi, ni, v, gi, gj);
         if (gi < g.m && gj < g.n && (!g.lower || gi >= gj)) C[gi + (size_t)gj * g.ldc] = acc[mi][ni][v];
       }
     }
