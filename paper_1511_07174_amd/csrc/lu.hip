@@ -760,8 +760,11 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
     }
     return CDS_SUCCESS;
   }
-  // look-ahead: s0 carries panels and the next panel's columns, s1 the rest.
-  hipEvent_t evP = c.ev[1], evR = c.ev[2];
+  // look-ahead: s0 carries panels and the next panel's columns, s1 the rest.  The rest of step
+  // k starts once the next panel's columns are updated: that short chain sits on the critical
+  // path and runs faster without the rest's interchanges and TRSM beside it, while the rest
+  // still overlaps the whole of the next panel.
+  hipEvent_t evL = c.ev[1], evR = c.ev[2];
   if (panel(0, std::min(nb, n), 0, s0) != hipSuccess) return CDS_HIP_ERROR;
   bool have_rest = false;
   for (int k = 0; k < n; k += nb, ++step) {
@@ -769,20 +772,17 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
     const int par = step & 1;
     const int kn = k + jb;                       // next panel start
     const int jbn = std::min(nb, n - kn);        // next panel width (<= 0 if none)
-    if (hipEventRecord(evP, s0) != hipSuccess) return CDS_HIP_ERROR;   // panel k done
-    // s1: rest of the trailing matrix and the left interchanges
-    if (hipStreamWaitEvent(s1, evP, 0) != hipSuccess) return CDS_HIP_ERROR;
-    if (jbn > 0) {
-      if (update(k, jb, par, kn + jbn, n, true, s1) != hipSuccess) return CDS_HIP_ERROR;
-    } else {
-      if (update(k, jb, par, n, n, true, s1) != hipSuccess) return CDS_HIP_ERROR;
-    }
     // s0: next panel's columns (need the previous rest update to have reached them)
     if (jbn > 0) {
       if (have_rest && hipStreamWaitEvent(s0, evR, 0) != hipSuccess) return CDS_HIP_ERROR;
       if (update(k, jb, par, kn, kn + jbn, false, s0) != hipSuccess) return CDS_HIP_ERROR;
-      if (panel(kn, jbn, par ^ 1, s0) != hipSuccess) return CDS_HIP_ERROR;
     }
+    // panel k (and, with a next panel, its columns) done
+    if (hipEventRecord(evL, s0) != hipSuccess) return CDS_HIP_ERROR;
+    if (jbn > 0 && panel(kn, jbn, par ^ 1, s0) != hipSuccess) return CDS_HIP_ERROR;
+    // s1: rest of the trailing matrix and the left interchanges
+    if (hipStreamWaitEvent(s1, evL, 0) != hipSuccess) return CDS_HIP_ERROR;
+    if (update(k, jb, par, jbn > 0 ? kn + jbn : n, n, true, s1) != hipSuccess) return CDS_HIP_ERROR;
     if (hipEventRecord(evR, s1) != hipSuccess) return CDS_HIP_ERROR;
     have_rest = true;
   }
