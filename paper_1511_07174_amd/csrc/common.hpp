@@ -332,6 +332,30 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
+// Column c of the inverse of the 16 x 16 diagonal block blk of the lower
+// triangle L (unit diagonal when UNIT), by forward substitution in FP64, into
+// Linv[blk * 256 + i * 16 + c]; rows of the block at or beyond jb act as the
+// identity.
+template <typename T, bool UNIT>
+__device__ __forceinline__ void diag_inv16_column(const T* L, int64_t lda, int jb, int blk, int c, double* Linv) {
+  const int r0 = blk * 16, rb = min(16, jb - r0);
+  double y[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    if (i >= rb) {
+      y[i] = (i == c) ? 1.0 : 0.0;
+      continue;
+    }
+    double s = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = 0; q < i; ++q)
+      if (q >= c) s -= (double)L[(r0 + i) + (size_t)(r0 + q) * lda] * y[q];
+    y[i] = (i < c) ? 0.0 : (UNIT ? s : s / (double)L[(r0 + i) + (size_t)(r0 + i) * lda]);
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) Linv[(size_t)blk * 256 + i * 16 + c] = y[i];
+}
+
 __device__ __forceinline__ void wave_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();

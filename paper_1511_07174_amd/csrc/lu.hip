@@ -39,6 +39,7 @@ struct PanelArgs {
   int cnt_stride;                                     // counts per matrix
   int* err;
   int G;
+  double* linv; int64_t strideI;   // L11's 16 x 16 diagonal-block inverses (nullptr: not formed here)
 };
 
 template <typename T, int W>
@@ -564,6 +565,14 @@ __global__ void __launch_bounds__(PNT, 2) panel_kernel(PanelArgs<T> P) {
       __syncthreads();   // Ubuf is reloaded by the next chunk
     }
   }
+  // The panel's top jb <= PNT rows, L11 among them, are rows of workgroup 0 and were written by
+  // its own threads: once they are all stored, it forms the inverses of L11's unit 16 x 16
+  // diagonal blocks for the TRSMs that follow.
+  if (P.linv != nullptr && g == 0) {
+    __syncthreads();
+    double* Li = P.linv + (size_t)b * P.strideI;
+    for (int t = tid; t < ((jb + 15) / 16) * 16; t += PNT) diag_inv16_column<T, true>(A, lda, jb, t >> 4, t & 15, Li);
+  }
 }
 
 // Apply the panel's interchanges (per-leaf move lists) to column ranges
@@ -685,6 +694,10 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
     P.cnt_stride = nleaves;
     P.err = c.err;
     P.G = (n - k + PNT - 1) / PNT;
+    double* li = linv + (size_t)parity * batch * inv_stride;
+    const bool fused_inv = jb <= PNT;   // then workgroup 0 holds all of L11
+    P.linv = fused_inv ? li : nullptr;
+    P.strideI = inv_stride;
     const double m = n - k;
     {
       KScope ks(c.timer, CDS_KC_PANEL, s, batch * (m * jb * jb - (double)jb * jb * jb / 3.0),
@@ -692,11 +705,10 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
       hipLaunchKernelGGL((panel_kernel<T, kLeaf>), dim3(P.G, batch), dim3(PNT), 0, s, P);
     }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || fused_inv) return e;
     // inverses of L11's 16 x 16 diagonal blocks for this panel's TRSMs
     KScope kt(c.timer, CDS_KC_TRSM, s, 0.0, 0.0);
-    return launch_diag_inv16<T>(A + k + (size_t)k * lda, lda, strideA, jb, 1, linv + (size_t)parity * batch * inv_stride,
-                                inv_stride, batch, s);
+    return launch_diag_inv16<T>(A + k + (size_t)k * lda, lda, strideA, jb, 1, li, inv_stride, batch, s);
   };
   // interchanges + trsm + gemm on columns [cb, ce) for the panel at k (width jb)
   auto update = [&](int k, int jb, int parity, int cb, int ce, bool left, hipStream_t s) -> hipError_t {

@@ -34,24 +34,8 @@ __global__ void __launch_bounds__(256) diag_inv16_kernel(const T* L0, int64_t ld
   const T* L = L0 + (size_t)b * strideA;
   double* Linv = Linv0 + (size_t)b * strideI;
   const int nblk = (jb + 15) / 16;
-  for (int t = blockIdx.x * 256 + threadIdx.x; t < nblk * 16; t += gridDim.x * 256) {
-    const int blk = t >> 4, c = t & 15, r0 = blk * 16, rb = min(16, jb - r0);
-    double y[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      if (i >= rb) {
-        y[i] = (i == c) ? 1.0 : 0.0;   // padding rows: identity
-        continue;
-      }
-      double s = (i == c) ? 1.0 : 0.0;
-#pragma unroll
-      for (int q = 0; q < i; ++q)
-        if (q >= c) s -= (double)L[(r0 + i) + (size_t)(r0 + q) * lda] * y[q];
-      y[i] = (i < c) ? 0.0 : (UNIT ? s : s / (double)L[(r0 + i) + (size_t)(r0 + i) * lda]);
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) Linv[(size_t)blk * 256 + i * 16 + c] = y[i];
-  }
+  for (int t = blockIdx.x * 256 + threadIdx.x; t < nblk * 16; t += gridDim.x * 256)
+    diag_inv16_column<T, UNIT>(L, lda, jb, t >> 4, t & 15, Linv);
 }
 
 // QG: 16-row groups per wave (4 waves x QG x 16 >= jb)
