@@ -46,7 +46,8 @@ def _timeit(fn, reps=2):
     return best
 
 
-def tune_getrf(sizes=(2048, 4096, 8192, 16384), dtypes=("f64", "f32"), candidates=(128, 192, 256, 384), seed=0):
+def tune_getrf(sizes=(2048, 4096, 8192, 16384), dtypes=("f64", "f32"), candidates=(128, 160, 192, 224, 256, 384),
+                seed=0):
     h = cds.handle()
     dev = torch.device("cuda", torch.cuda.current_device())
     g = torch.Generator(device=dev).manual_seed(seed)
