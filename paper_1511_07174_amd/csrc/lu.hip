@@ -56,29 +56,42 @@ struct SlotLayout {
   __host__ __device__ int64_t sw(int par, int e) const { return 2 * cs_par() + par * sw_par() + (int64_t)e * jb * LLW; }
 };
 
-// Gather half of a column step for up to 64 workgroups (one-word values).
-// Lane i polls workgroup i's header, and lane l < wl word l of row j.  Each
-// poll round also fetches, with one coalesced load, the candidate row of the
-// best header seen so far.  The loop ends when every header and row j are in
-// and the row held is that of the final best.  If the last header to arrive
-// does not change the best, the pivot row is then already in registers and
-// costs no round trip of its own.  Same outputs as colstep_exchange.
+// Gather half of a column step for up to 64 workgroups.  Lane i polls
+// workgroup i's header, and lane l < wl value l of row j.  Each poll round also
+// fetches, with one coalesced load per word, the candidate row of the best
+// header seen so far.  The loop ends when every header and row j are in and
+// the row held is that of the final best.  If the last header to arrive does
+// not change the best, the pivot row is then already in registers and costs no
+// round trip of its own.  Same outputs as colstep_exchange.
 template <typename T, int W>
 __device__ __forceinline__ void colstep_gather_fast(const uint64_t* slots, const SlotLayout<T, W>& L, int m, int wl,
                                                     int cc, int j, int par, uint32_t flag, T* prow, T* prm, T* jrow,
                                                     int* s_p, int* err) {
-  static_assert(LLWords<T>::n == 1, "one word per value");
+  constexpr int LLW = LLWords<T>::n;
   const int lane = lane_id();
   const bool hv = lane < L.G;
   const uint64_t* hp = slots + L.hdr(par, hv ? lane : 0);
-  const uint64_t* jp = slots + L.rowj(par) + (lane < wl ? lane : 0);
+  const uint64_t* jp = slots + L.rowj(par) + (lane < wl ? lane : 0) * LLW;
   bool h_ok = !hv, j_ok = lane >= wl, r_ok = true;
   T hm = (T)-1;
   int hr = 0x7fffffff;
-  uint32_t jv = 0u, rv = 0u;
+  uint32_t jv[LLW], rv[LLW];
+#pragma unroll
+  for (int h = 0; h < LLW; ++h) jv[h] = rv[h] = 0u;
   int row_of = -1;   // workgroup whose candidate row rv holds (wave-uniform)
   T bm;
   int br;
+  auto value = [](const uint32_t* w) -> T {
+    if constexpr (LLW == 2)
+      return __longlong_as_double((long long)(((uint64_t)w[1] << 32) | (uint64_t)w[0]));
+    else
+      return __uint_as_float(w[0]);
+  };
+  auto fresh = [&](const uint64_t* w, int nw) {
+    bool ok = true;
+    for (int h = 0; h < nw; ++h) ok = ok && (uint32_t)(w[h] >> 32) == flag;
+    return ok;
+  };
   long long spins = 0;
   while (true) {
     wave_pivot_search<T>(hm, hr, h_ok, bm, br);
@@ -88,27 +101,44 @@ __device__ __forceinline__ void colstep_gather_fast(const uint64_t* slots, const
       r_ok = lane >= wl || bw < 0;
     }
     if (__all(h_ok && j_ok && r_ok)) break;
-    uint64_t hw0 = 0, hw1 = 0, rw = 0, jw = 0;
+    uint64_t hw[LLW + 1], rw[LLW], jw[LLW];
+#pragma unroll
+    for (int h = 0; h < LLW + 1; ++h) hw[h] = 0;
+#pragma unroll
+    for (int h = 0; h < LLW; ++h) rw[h] = jw[h] = 0;
     if (!h_ok) {
-      hw0 = __hip_atomic_load(const_cast<uint64_t*>(hp), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      hw1 = __hip_atomic_load(const_cast<uint64_t*>(hp + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+      for (int h = 0; h < LLW + 1; ++h)
+        hw[h] = __hip_atomic_load(const_cast<uint64_t*>(hp + h), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (!r_ok)
-      rw = __hip_atomic_load(const_cast<uint64_t*>(slots + L.cand(par, row_of) + lane), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-    if (!j_ok) jw = __hip_atomic_load(const_cast<uint64_t*>(jp), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (!h_ok && (uint32_t)(hw0 >> 32) == flag && (uint32_t)(hw1 >> 32) == flag) {
+    if (!r_ok) {
+      const uint64_t* rp = slots + L.cand(par, row_of) + lane * LLW;
+#pragma unroll
+      for (int h = 0; h < LLW; ++h)
+        rw[h] = __hip_atomic_load(const_cast<uint64_t*>(rp + h), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!j_ok) {
+#pragma unroll
+      for (int h = 0; h < LLW; ++h)
+        jw[h] = __hip_atomic_load(const_cast<uint64_t*>(jp + h), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!h_ok && fresh(hw, LLW + 1)) {
       h_ok = true;
-      hm = __uint_as_float((uint32_t)hw0);
-      hr = (int)(uint32_t)hw1;
+      uint32_t mw[LLW];
+#pragma unroll
+      for (int h = 0; h < LLW; ++h) mw[h] = (uint32_t)hw[h];
+      hm = value(mw);
+      hr = (int)(uint32_t)hw[LLW];
     }
-    if (!r_ok && (uint32_t)(rw >> 32) == flag) {
+    if (!r_ok && fresh(rw, LLW)) {
       r_ok = true;
-      rv = (uint32_t)rw;
+#pragma unroll
+      for (int h = 0; h < LLW; ++h) rv[h] = (uint32_t)rw[h];
     }
-    if (!j_ok && (uint32_t)(jw >> 32) == flag) {
+    if (!j_ok && fresh(jw, LLW)) {
       j_ok = true;
-      jv = (uint32_t)jw;
+#pragma unroll
+      for (int h = 0; h < LLW; ++h) jv[h] = (uint32_t)jw[h];
     }
     ++spins;
     if ((spins & 1023) == 0) {
@@ -124,10 +154,10 @@ __device__ __forceinline__ void colstep_gather_fast(const uint64_t* slots, const
   const int p = (br >= j && br < m) ? br : j;
   const bool from_cand = p == br;
   if (lane < W) {
-    const T x = lane < wl ? __uint_as_float(from_cand ? rv : jv) : (T)0;
+    const T x = lane < wl ? value(from_cand ? rv : jv) : (T)0;
     prow[lane] = x;
     prm[lane] = lane > cc ? x : (T)0;
-    if (p != j) jrow[lane] = lane < wl ? __uint_as_float(jv) : (T)0;
+    if (p != j) jrow[lane] = lane < wl ? value(jv) : (T)0;
   }
   if (lane == 0) *s_p = p;
 }
@@ -167,6 +197,8 @@ __device__ __forceinline__ void colstep_exchange(uint64_t* slots, const SlotLayo
     ll_store_val(slots + L.cand(par, g) + lane * LLW, mag >= (T)0 ? rowbuf[(row - g * PNT) >> 6][lane] : (T)0,
                  flag);
   if (j / PNT == g && lane < wl) ll_store_val(slots + L.rowj(par) + lane * LLW, jbuf[lane], flag);
+  // one-word values only: for FP64 the per-round pivot reduction over two-word magnitudes cost more
+  // than the saved round trip (FP64 getrf+getrs at n = 16384: 158.5 ms against 154.6 ms)
   if constexpr (LLW == 1) {
     if (L.G <= kWave) {
       colstep_gather_fast<T, W>(slots, L, m, wl, cc, j, par, flag, prow, prm, jrow, s_p, err);
