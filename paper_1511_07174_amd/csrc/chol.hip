@@ -125,7 +125,8 @@ __device__ __forceinline__ T lane_get(T v, int l) {
 constexpr int PJB = 128, PLD = PJB + 1;
 
 template <typename T>
-__global__ void __launch_bounds__(256) potf2_lds_kernel(T* A, int64_t lda, int k, int jb, int32_t* info) {
+__global__ void __launch_bounds__(256) potf2_lds_kernel(T* A, int64_t lda, int k, int jb, int32_t* info,
+                                                        double* linv) {
   __shared__ T Ds[PJB * PLD];   // (r, c) at Ds[c * PLD + r]
   __shared__ T colb[64];
   __shared__ T rdiag[SB];
@@ -259,6 +260,10 @@ __global__ void __launch_bounds__(256) potf2_lds_kernel(T* A, int64_t lda, int k
     const int r = idx % jb, c = idx / jb;
     if (r >= c) D[r + (size_t)c * lda] = Ds[c * PLD + r];
   }
+  // the inverses of the factor's 16 x 16 diagonal blocks for the TRSM below it, from the block in LDS
+  // (after a failed pivot the TRSM does not run and these are never read)
+  if (linv != nullptr)
+    for (int t = tid; t < ((jb + 15) / 16) * 16; t += 256) diag_inv16_column<T, false>(Ds, PLD, jb, t >> 4, t & 15, linv);
 }
 
 }  // namespace
@@ -283,7 +288,8 @@ cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int
     {
       KScope ks(c.timer, CDS_KC_PANEL, st, (double)jb * jb * jb / 3.0, (double)jb * jb * sizeof(T));
       if (jb <= PJB) {
-        hipLaunchKernelGGL((potf2_lds_kernel<T>), dim3(1), dim3(256), 0, st, A, lda, k, jb, info);
+        hipLaunchKernelGGL((potf2_lds_kernel<T>), dim3(1), dim3(256), 0, st, A, lda, k, jb, info,
+                           n - k - jb > 0 ? linv : nullptr);
       } else {
         const size_t psm = sizeof(T) * (size_t)(SB + 1) * (SB + jb);
         hipLaunchKernelGGL((potf2_kernel<T>), dim3(1), dim3(256), psm, st, A, lda, k, jb, info);
@@ -295,7 +301,7 @@ cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int
     {
       // L21 = A21 L11^{-T}: the transposed column solve L11 L21^T = A21^T on MFMA tiles
       KScope ks(c.timer, CDS_KC_TRSM, st, (double)jb * jb * rem, 0.0);
-      if (launch_diag_inv16<T>(A + k + (size_t)k * lda, lda, 0, jb, 0, linv, 0, 1, st) != hipSuccess)
+      if (jb > PJB && launch_diag_inv16<T>(A + k + (size_t)k * lda, lda, 0, jb, 0, linv, 0, 1, st) != hipSuccess)
         return CDS_HIP_ERROR;
       if (launch_trsm16<T>(A + k + (size_t)k * lda, lda, 0, linv, 0, A + (k + jb) + (size_t)k * lda, lda, 0, jb, rem,
                            1, 1, info, st) != hipSuccess)
