@@ -86,10 +86,14 @@ __global__ void __launch_bounds__(256) trsm16_kernel(const T* L0, int64_t lda, i
     }
   };
   prefetch(0);
+  // the diagonal-block inverses are read one block ahead too, off the dependency chain
+  double li_next = Linv[tid];
   for (int blk = 0; blk < nblk; ++blk) {
     const int r0 = 16 * blk;
+    const double li_cur = li_next;
+    if (blk + 1 < nblk) li_next = Linv[(size_t)(blk + 1) * 256 + tid];
     __syncthreads();   // X loaded / the previous block's update done; Li free
-    Li[tid >> 4][tid & 15] = Linv[(size_t)blk * 256 + tid];
+    Li[tid >> 4][tid & 15] = li_cur;
     __syncthreads();
     // X_b <- inv(L_bb) X_b: wave 0 and 1 each own a 16-column tile
     if (wave < 2) {
