@@ -25,7 +25,6 @@ namespace cds {
 
 namespace {
 
-constexpr int TCW = 32;   // columns of B per workgroup
 
 template <typename T, bool UNIT>
 __global__ void __launch_bounds__(256) diag_inv16_kernel(const T* L0, int64_t lda, int64_t strideA, int jb,
@@ -38,8 +37,8 @@ __global__ void __launch_bounds__(256) diag_inv16_kernel(const T* L0, int64_t ld
     diag_inv16_column<T, UNIT>(L, lda, jb, t >> 4, t & 15, Linv);
 }
 
-// QG: 16-row groups per wave (4 waves x QG x 16 >= jb)
-template <typename T, bool TRANS, int QG>
+// QG: 16-row groups per wave (4 waves x QG x 16 >= jb); TCW: columns of B per workgroup (16 or 32)
+template <typename T, bool TRANS, int QG, int TCW>
 __global__ void __launch_bounds__(256) trsm16_kernel(const T* L0, int64_t lda, int64_t strideA, const double* Linv0,
                                                      int64_t strideI, T* B0, int64_t ldb, int64_t strideB, int jb,
                                                      int ncols, const int32_t* guard) {
@@ -95,8 +94,8 @@ __global__ void __launch_bounds__(256) trsm16_kernel(const T* L0, int64_t lda, i
     __syncthreads();   // X loaded / the previous block's update done; Li free
     Li[tid >> 4][tid & 15] = li_cur;
     __syncthreads();
-    // X_b <- inv(L_bb) X_b: wave 0 and 1 each own a 16-column tile
-    if (wave < 2) {
+    // X_b <- inv(L_bb) X_b: waves 0 .. TCW / 16 - 1 each own a 16-column tile
+    if (wave < TCW / 16) {
       d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int kc = 0; kc < 4; ++kc) {
@@ -120,7 +119,7 @@ __global__ void __launch_bounds__(256) trsm16_kernel(const T* L0, int64_t lda, i
       const int g = wave + 4 * q;
       if (g > blk && g < nblk) {
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
+        for (int ct = 0; ct < TCW / 16; ++ct) {
           acc_t acc;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
@@ -182,24 +181,24 @@ hipError_t launch_trsm16(const T* L, int64_t lda, int64_t strideA, const double*
                          hipStream_t s) {
   if (jb <= 0 || ncols <= 0 || batch <= 0) return hipSuccess;
   const int nblk = (jb + 15) / 16;
-  const size_t sm = (size_t)nblk * 16 * (TCW + 1) * sizeof(T);
-  const dim3 grid((ncols + TCW - 1) / TCW, batch);
   // at most 512 rows: 4 waves x 8 groups of 16
   if (jb > 512) return hipErrorInvalidValue;
+  // narrow calls (a look-ahead's next panel) take 16-column slices: twice the workgroups on a
+  // dependency chain whose length does not shrink with the width
+  const bool narrow = (int64_t)batch * ncols <= 1024;
+  auto go = [&](auto kern, int tcw) {
+    const size_t sm = (size_t)nblk * 16 * (tcw + 1) * sizeof(T);
+    const dim3 grid((ncols + tcw - 1) / tcw, batch);
+    hipLaunchKernelGGL(kern, grid, dim3(256), sm, s, L, lda, strideA, Linv, strideI, B, ldb, strideB, jb, ncols, guard);
+  };
   if (jb <= 256) {
-    if (trans)
-      hipLaunchKernelGGL((trsm16_kernel<T, true, 4>), grid, dim3(256), sm, s, L, lda, strideA, Linv, strideI, B, ldb,
-                         strideB, jb, ncols, guard);
-    else
-      hipLaunchKernelGGL((trsm16_kernel<T, false, 4>), grid, dim3(256), sm, s, L, lda, strideA, Linv, strideI, B, ldb,
-                         strideB, jb, ncols, guard);
+    if (narrow) {
+      if (trans) go(trsm16_kernel<T, true, 4, 16>, 16); else go(trsm16_kernel<T, false, 4, 16>, 16);
+    } else {
+      if (trans) go(trsm16_kernel<T, true, 4, 32>, 32); else go(trsm16_kernel<T, false, 4, 32>, 32);
+    }
   } else {
-    if (trans)
-      hipLaunchKernelGGL((trsm16_kernel<T, true, 8>), grid, dim3(256), sm, s, L, lda, strideA, Linv, strideI, B, ldb,
-                         strideB, jb, ncols, guard);
-    else
-      hipLaunchKernelGGL((trsm16_kernel<T, false, 8>), grid, dim3(256), sm, s, L, lda, strideA, Linv, strideI, B, ldb,
-                         strideB, jb, ncols, guard);
+    if (trans) go(trsm16_kernel<T, true, 8, 32>, 32); else go(trsm16_kernel<T, false, 8, 32>, 32);
   }
   return hipGetLastError();
 }
