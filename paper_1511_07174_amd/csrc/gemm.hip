@@ -29,7 +29,7 @@ constexpr int BM = 128, BN = 128, NT = 256;
 template <typename T, int MODE> struct GemmCfg;
 // MODE 0: native precision MFMA
 template <> struct GemmCfg<double, 0> { static constexpr int BK = 16; };
-template <> struct GemmCfg<float, 0> { static constexpr int BK = 32; };
+template <> struct GemmCfg<float, 0> { static constexpr int BK = 16; };
 // MODE 1: bf16 operands, MODE 2: fp16 operands (T = float storage)
 template <> struct GemmCfg<float, 1> { static constexpr int BK = 32; };
 template <> struct GemmCfg<float, 2> { static constexpr int BK = 32; };
@@ -70,7 +70,7 @@ __device__ __forceinline__ T ldg_or_zero(const T* p, bool ok) { return ok ? *p :
 // dimensions); edge vectors fall back to element loads with bounds checks.
 // ------------------------------------------------------------------------------------
 template <typename T, bool VEC>
-__global__ void __launch_bounds__(NT, 2)
+__global__ void __launch_bounds__(NT, (sizeof(T) == 4 && VEC) ? 3 : 2)
 gemm_native_kernel(GemmArgs<T> g) {
   if (g.guard && *g.guard != 0) return;
   constexpr int BK = GemmCfg<T, 0>::BK;
