@@ -54,6 +54,8 @@ def lib():
         I64 = ctypes.c_int64
         L.oracle_dgetrf.restype = I64
         L.oracle_dgetrf.argtypes = [I64, P, I64, P]
+        L.oracle_sgetrf.restype = I64
+        L.oracle_sgetrf.argtypes = [I64, P, I64, P]
         L.oracle_dgetrs.restype = None
         L.oracle_dgetrs.argtypes = [ctypes.c_int, I64, I64, P, I64, P, P, I64]
         L.oracle_dpotrf.restype = I64
@@ -97,6 +99,16 @@ def getrf(A):
     assert LU.shape == (n, n)
     ipiv = np.zeros(n, dtype=np.int32)
     info = lib().oracle_dgetrf(n, _ptr(LU), max(1, n), _ptr(ipiv))
+    return LU, ipiv, int(info)
+
+
+def sgetrf(A):
+    """GEPP carried out entirely in FP32 (A is rounded to FP32 first): returns (LU float32, ipiv, info)."""
+    LU = np.array(A, dtype=np.float32, order="F", copy=True)
+    n = LU.shape[0]
+    assert LU.shape == (n, n)
+    ipiv = np.zeros(n, dtype=np.int32)
+    info = lib().oracle_sgetrf(n, _ptr(LU), max(1, n), _ptr(ipiv))
     return LU, ipiv, int(info)
 
 
@@ -172,6 +184,32 @@ def ipiv_to_perm(ipiv):
         j = int(ipiv[k]) - 1
         p[k], p[j] = p[j], p[k]
     return p
+
+
+def first_pivot_mismatch(ipiv_test, LU_ref, ipiv_ref):
+    """Compare a pivot sequence with the oracle's.  Returns (k, mult): k = the first step whose pivot
+    differs (len(ipiv) when none does) and mult = |l| of the row the tested sequence chose at step k,
+    read from the oracle's own factor L.  Up to step k both sequences interchanged the same rows, so
+    that row's multiplier in the oracle's elimination is |a(chosen, k)| / |a(pivot, k)| <= 1, and a
+    value within rounding of 1 means the two rows tied for the pivot (a legitimate difference)."""
+    a = np.asarray(ipiv_test).astype(np.int64) - 1
+    b = np.asarray(ipiv_ref).astype(np.int64) - 1
+    n = len(b)
+    diff = np.nonzero(a != b)[0]
+    if len(diff) == 0:
+        return n, 1.0
+    k = int(diff[0])
+    pos = int(a[k])
+    # the oracle's interchange at step k, then every later one, moves that row
+    if pos == k:
+        pos = int(b[k])
+    for j in range(k + 1, n):
+        q = int(b[j])
+        if pos == j:
+            pos = q
+        elif pos == q:
+            pos = j
+    return k, float(abs(np.asarray(LU_ref)[pos, k]))
 
 
 def unpack_lu(LU):

@@ -95,6 +95,50 @@ int64_t oracle_dgetrf(int64_t n, double* A, int64_t lda, int32_t* ipiv) {
 }
 
 /*
+ * The same elimination carried out in single precision (the paper runs its
+ * solvers in single as well as double precision, Sec. 4).  Every stored value,
+ * product and difference is a float, so the pivot decisions are taken in FP32,
+ * the precision of the FP32 factorization it is compared with.  Same steps and
+ * conventions as oracle_dgetrf.  Returns info.
+ */
+int64_t oracle_sgetrf(int64_t n, float* A, int64_t lda, int32_t* ipiv) {
+  int64_t info = 0;
+  for (int64_t k = 0; k < n; ++k) {
+    int64_t mu = k;
+    float best = fabsf(AT(A, lda, k, k));
+    for (int64_t i = k + 1; i < n; ++i) {
+      float v = fabsf(AT(A, lda, i, k));
+      if (v > best) { best = v; mu = i; }
+    }
+    ipiv[k] = (int32_t)(mu + 1);
+    if (mu != k) {
+      for (int64_t j = 0; j < n; ++j) {
+        float t = AT(A, lda, k, j);
+        AT(A, lda, k, j) = AT(A, lda, mu, j);
+        AT(A, lda, mu, j) = t;
+      }
+    }
+    float piv = AT(A, lda, k, k);
+    if (piv != 0.0f) {
+      for (int64_t i = k + 1; i < n; ++i) AT(A, lda, i, k) = AT(A, lda, i, k) / piv;
+#pragma omp parallel for schedule(static) if (n - k > 256)
+      for (int64_t j = k + 1; j < n; ++j) {
+        float ukj = AT(A, lda, k, j);
+        if (ukj != 0.0f) {
+          for (int64_t i = k + 1; i < n; ++i) {
+            float prod = AT(A, lda, i, k) * ukj;
+            AT(A, lda, i, j) = AT(A, lda, i, j) - prod;
+          }
+        }
+      }
+    } else if (info == 0) {
+      info = k + 1;
+    }
+  }
+  return info;
+}
+
+/*
  * Second step of the direct method (Sec. 2): with P A = L U,
  *   trans = 0: solve A X = B:   apply the interchanges to B in order k = 0..n-1,
  *              forward substitution L Y = P B (unit diagonal), back substitution U X = Y.

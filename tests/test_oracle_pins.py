@@ -324,3 +324,146 @@ def test_adjoint_matches_central_differences():
         E[i, j] = h
         fd = (loss(A + E, b) - loss(A - E, b)) / (2 * h)
         assert abs(fd - Abar[i, j]) <= 1e-7 * max(1.0, abs(Abar[i, j]))
+
+
+# ---------------------------------------------------------------- the checkers themselves
+def _exact_eta(A, X, B):
+    """Normwise backward error max_c ||b_c - A x_c||_inf / (||A||_inf ||x_c||_inf) in exact rationals."""
+    n = A.shape[0]
+    rows = [sum(abs(Fraction(float(A[i, j]))) for j in range(n)) for i in range(n)]
+    nA = max(rows)
+    worst = Fraction(0)
+    for c in range(X.shape[1]):
+        r = exact.residual(A.tolist(), X[:, c].tolist(), B[:, c].tolist())
+        xm = max(abs(Fraction(float(v))) for v in X[:, c])
+        worst = max(worst, max(abs(v) for v in r) / (nA * xm))
+    return worst
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_eta_inf_equals_exact_rational(seed):
+    """eta_inf (double-double residual, row-sum norm, max over |x| and over columns) against the same
+    quantity in exact rational arithmetic: at most a few units of rounding apart."""
+    g = synth.rng(400 + seed)
+    n = int(g.integers(3, 8))
+    A = g.integers(-9, 10, size=(n, n)).astype(np.float64)
+    if exact.det_leibniz(A) == 0:
+        A += 10 * np.eye(n)
+    B = g.integers(-9, 10, size=(n, 3)).astype(np.float64)
+    LU, ipiv, info = oracle.getrf(A)
+    X = oracle.getrs(LU, ipiv, B)
+    X[:, 1] *= 1.0 + 2.0 ** -40          # columns with different backward errors
+    X[:, 2] += 2.0 ** -30
+    ref = _exact_eta(A, X, B)
+    got = oracle.eta_inf(A, X, B)
+    assert ref > 0
+    assert abs(Fraction(got) - ref) <= ref * Fraction(8) * Fraction(2) ** -52
+    # transposed form: A^T x = b
+    Xt = oracle.getrs(LU, ipiv, B, trans=True)
+    Xt[:, 0] *= 1.0 - 2.0 ** -41
+    ref_t = _exact_eta(A.T.copy(), Xt, B)
+    got_t = oracle.eta_inf(A, Xt, B, trans=True)
+    assert abs(Fraction(got_t) - ref_t) <= ref_t * Fraction(8) * Fraction(2) ** -52
+
+
+def test_norm_inf_is_the_max_row_sum():
+    """Hand matrices whose row sums, column sums and signed sums all differ."""
+    A = np.array([[1.0, -10.0], [2.0, 0.0], [-3.0, 3.0]])      # rows 11, 2, 6; columns 6, 13
+    assert oracle.norm_inf(A) == 11.0
+    assert oracle.norm_inf(A.T) == 13.0
+    B = np.array([[0.0, 5.0], [-4.0, -4.0]])                     # rows 5, 8; columns 4, 9; signed row sum -8
+    assert oracle.norm_inf(B) == 8.0
+    assert oracle.norm_inf(np.array([[-2.5]])) == 2.5
+    assert np.isnan(oracle.norm_inf(np.array([[1.0, 0.0], [np.nan, 1.0]])))
+    # eta picks the worst column, and divides by max |x| of that column, not of all of X
+    A = np.eye(2)
+    X = np.array([[1.0, 4.0], [0.5, 0.0]])
+    B = np.array([[1.0, 4.0], [0.5, 1.0]])                       # column 1: r = (0, 1), ||x|| = 4
+    assert oracle.eta_inf(A, X, B) == 0.25
+
+
+def test_reconstruction_checkers_flag_planted_mistakes():
+    """rho_lu, freivalds_lu and rho_llt are zero (to rounding) on exact factors and orders of magnitude
+    above their thresholds when one entry of a factor is wrong, the permutation is dropped or
+    inverted, or the factors are transposed."""
+    n = 64
+    A, L, U, perm = synth.dyadic_plu(n, 12)
+    LU = np.tril(L, -1) + U
+    ipiv = synth.perm_to_ipiv(perm)
+    assert oracle.rho_lu(A, LU, ipiv) == 0.0
+    assert oracle.freivalds_lu(A, LU, ipiv) <= 8 * oracle.EPS
+    bad = LU.copy()
+    bad[40, 7] += 2.0 ** -8                                      # one entry of L
+    assert oracle.rho_lu(A, bad, ipiv) > 1e6
+    assert oracle.freivalds_lu(A, bad, ipiv) > 1e-6
+    bad = LU.copy()
+    bad[3, 50] -= 2.0 ** -8                                      # one entry of U
+    assert oracle.rho_lu(A, bad, ipiv) > 1e6
+    assert oracle.freivalds_lu(A, bad, ipiv) > 1e-6
+    ident = np.arange(1, n + 1, dtype=np.int32)                  # permutation dropped
+    assert oracle.rho_lu(A, LU, ident) > 1e6
+    assert oracle.freivalds_lu(A, LU, ident) > 1e-3
+    inv = synth.perm_to_ipiv(np.argsort(perm))                   # permutation inverted
+    assert oracle.rho_lu(A, LU, inv) > 1e6
+    assert oracle.freivalds_lu(A, LU, inv) > 1e-3
+    assert oracle.rho_lu(A, LU.T.copy(), ipiv) > 1e6            # transposed factors
+    # Cholesky: the exact Pascal factor and a perturbed one
+    P = synth.pascal(20)
+    Lp = synth.pascal_factor(20)
+    assert oracle.rho_llt(P, Lp) == 0.0
+    badL = Lp.copy()
+    badL[15, 3] += 1.0
+    assert oracle.rho_llt(P, badL) > 1e6
+    assert oracle.rho_llt(P, Lp.T.copy()) > 1e6                  # the upper triangle is ignored: L^T reads as diag only
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (9, 1), (64, 2), (300, 3)])
+def test_sgetrf_dyadic_bitwise(n, seed):
+    """The FP32 elimination reproduces the exact dyadic factors too: every intermediate of this
+    construction is exact in single precision."""
+    A, L, U, perm = synth.dyadic_plu(n, seed)
+    LU, ipiv, info = oracle.sgetrf(A)
+    assert LU.dtype == np.float32 and info == 0
+    Lr, Ur = oracle.unpack_lu(LU.astype(np.float64))
+    assert np.array_equal(Lr, L) and np.array_equal(Ur, U)
+    assert np.array_equal(ipiv, synth.perm_to_ipiv(perm))
+
+
+def test_sgetrf_is_single_precision_gepp():
+    """Wilkinson ties (no interchange, U's last column 2^i), zero pivots as in FP64, and random FP32
+    inputs: pivots of exact GEPP on the same FP32 values (no near ties), factors within FP32 rounding;
+    the FP64 factors of the same input differ from them by far more than FP64 rounding."""
+    W = synth.wilkinson(20)
+    LU, ipiv, info = oracle.sgetrf(W)
+    assert np.array_equal(ipiv, np.arange(1, 21)) and np.array_equal(LU[:, 19], 2.0 ** np.arange(20))
+    Z = np.array([[0.0, 1.0, 2.0], [0.0, 2.0, 4.0], [0.0, 8.0, 3.0]])
+    assert oracle.sgetrf(Z)[2] == oracle.getrf(Z)[2] == 1
+    g = synth.rng(501)
+    A = g.uniform(-1, 1, (7, 7)).astype(np.float32).astype(np.float64)
+    Lx, Ux, pivx, _ = exact.gepp(A)
+    LU, ipiv, info = oracle.sgetrf(A)
+    assert list(ipiv) == pivx
+    Uf = np.array([[float(v) for v in row] for row in Ux])
+    Lf = np.array([[float(v) for v in row] for row in Lx])
+    L32, U32 = oracle.unpack_lu(LU.astype(np.float64))
+    scale = np.max(np.abs(Uf))
+    assert np.max(np.abs(U32 - Uf)) <= 64 * 2.0 ** -24 * scale
+    assert np.max(np.abs(L32 - Lf)) <= 64 * 2.0 ** -24 * max(1.0, np.max(np.abs(Lf)))
+    LU64, _, _ = oracle.getrf(A)
+    assert np.max(np.abs(LU64 - LU.astype(np.float64))) > 1e-12
+
+
+def test_first_pivot_mismatch_reads_the_tie():
+    """The pivot comparison helper: equal sequences report n; a sequence that takes the other row of
+    an exact tie reports that step with multiplier 1; a wrong non-tied row reports |l| < 1."""
+    A = np.array([[1.0, 2.0, 0.0], [-1.0, 0.0, 1.0], [0.5, 1.0, 3.0]])
+    LU, ipiv, _ = oracle.getrf(A)
+    assert oracle.first_pivot_mismatch(ipiv, LU, ipiv) == (3, 1.0)
+    alt = ipiv.copy()
+    alt[0] = 2                                                   # rows 0 and 1 tie at |1|
+    k, mult = oracle.first_pivot_mismatch(alt, LU, ipiv)
+    assert k == 0 and mult == 1.0
+    alt = ipiv.copy()
+    alt[0] = 3                                                   # row 2 has |0.5|: no tie
+    k, mult = oracle.first_pivot_mismatch(alt, LU, ipiv)
+    assert k == 0 and mult == 0.5
