@@ -104,6 +104,20 @@ cds_status_t cds_set_option(cds_handle_t handle, cds_option_t option, int64_t va
  * of (key, dtype) is used.  value <= 0 is rejected. */
 cds_status_t cds_tune_set(cds_handle_t handle, cds_tune_key_t key, cds_dtype_t dtype, int64_t n_max, int64_t value);
 cds_status_t cds_tune_clear(cds_handle_t handle);
+/* Install the autotuner's table from a JSON file (host work only: the file is
+ * read and parsed on the host, nothing is enqueued).  The file is an object
+ * with an "entries" array of {"key": "getrf_nb" | "potrf_nb" | "vbatch_tile",
+ * "dtype": "f64" | "f32", "n_max": int, "value": int} records (the form the
+ * autotuner writes); other members are ignored.  Every entry must pass the
+ * checks of cds_tune_set, else CDS_INVALID_VALUE; a table whose "arch" member
+ * names another device than gfx950 gives CDS_ARCH_MISMATCH.  On any error the
+ * handle's table is left unchanged; on success it is replaced by the file's.
+ * The tuned quantities are the block size of the blocked factorizations (the
+ * rank of the delayed update, Sec. 2) and the batched kernel's tile width. */
+cds_status_t cds_tune(cds_handle_t handle, const char* table_path);
+/* Validate a table file as cds_tune would, without a handle (no GPU needed):
+ * *h_entries receives the number of entries on success. */
+cds_status_t cds_tune_check(const char* table_path, int64_t* h_entries);
 /* Synchronises the handle's stream, then reads and clears the device error
  * word of the workspace: *h_err = 0 when every bounded wait completed. */
 cds_status_t cds_device_error(cds_handle_t handle, int32_t* h_err);

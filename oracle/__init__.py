@@ -257,6 +257,26 @@ def freivalds_lu(A, LU, ipiv, nprobe: int = 8, seed: int = 0):
     return worst
 
 
+def freivalds_llt(A, L, nprobe: int = 8, seed: int = 0):
+    """max_v ||A v - L (L^T v)||_inf / (||A||_inf ||v||_inf) over random probes, with A read from its lower
+    triangle (symmetric); O(n^2) per probe."""
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Ls = np.tril(np.asarray(L, dtype=np.float64))
+    Al = np.tril(A)
+    nA = None
+    worst = 0.0
+    for _ in range(nprobe):
+        v = rng.uniform(-1.0, 1.0, n)
+        av = Al @ v + np.tril(A, -1).T @ v
+        llv = Ls @ (Ls.T @ v)
+        if nA is None:
+            nA = norm_inf(Al + np.tril(A, -1).T)
+        worst = max(worst, float(np.max(np.abs(av - llv)) / (nA * np.max(np.abs(v)))))
+    return worst
+
+
 def solve_refined(A, B, steps: int = 3):
     """Reference solution: GEPP solve plus a few steps of refinement with the double-double residual."""
     LU, ipiv, info = getrf(A)
@@ -279,6 +299,22 @@ def adjoint(A, x, xbar):
         bbar = bbar + getrs(LU, ipiv, residual_dd(A, bbar, xbar, trans=True), trans=True)
     Abar = -np.outer(bbar, x) if np.ndim(x) == 1 else -(_as2d(bbar) @ _as2d(x).T)
     return Abar, bbar
+
+
+def householder_inverse(vs_left, vs_right, sigma):
+    """Dense A^{-1} = H2^T diag(1/sigma) H1^T for A = H1 diag(sigma) H2 (see householder_solve), built by
+    applying the reflectors to diag(1/sigma): O(n^2) per reflector.  Used for the exact kappa_inf."""
+    n = len(sigma)
+    M = np.diag(1.0 / np.asarray(sigma, dtype=np.float64))
+    # rows: M <- M H1^T, the left reflectors last-to-first from the right (H1^T = Hd Hc Hb Ha)
+    for v in reversed(vs_left):
+        w = M @ v
+        M -= np.outer(w, (2.0 / (v @ v)) * v)
+    # columns: M <- H2^T M = Hd Hc Hb Ha M, so Ha acts first
+    for v in vs_right:
+        w = v @ M
+        M -= np.outer((2.0 / (v @ v)) * v, w)
+    return M
 
 
 def householder_solve(vs_left, vs_right, sigma, b):

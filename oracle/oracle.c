@@ -185,24 +185,38 @@ void oracle_dgetrs(int trans, int64_t n, int64_t nrhs, const double* LU, int64_t
 }
 
 /*
- * Cholesky A = L L^T of an SPD matrix (Sec. 2, "In the case of SPD matrices,
- * we have A = LL^t"), lower triangle, column (gaxpy / jki) form:
+ * Cholesky A = L L^T of an SPD matrix (Sec. 2: the symmetric positive
+ * definite case of the direct method), lower triangle, column (gaxpy / jki)
+ * form:
  *   s = a_jj - sum_{k<j} l_jk^2;  if !(s > 0): info = j + 1, stop;
  *   l_jj = sqrt(s);  l_ij = (a_ij - sum_{k<j} l_ik l_jk) / l_jj  (i > j).
+ * Every sum runs over k = 0, 1, ..., j-1 in that order.  The rows i > j are
+ * taken in chunks, and inside a chunk the loop over k is the outer one, so the
+ * columns of L are read contiguously; each row still subtracts its terms in
+ * the order k = 0..j-1, so the rounding is that of the formula as written.
  * Reads and writes the lower triangle only.  Returns info.
  */
 int64_t oracle_dpotrf(int64_t n, double* A, int64_t lda) {
+  enum { CH = 256 };
   for (int64_t j = 0; j < n; ++j) {
     double s = AT(A, lda, j, j);
     for (int64_t k = 0; k < j; ++k) s = s - AT(A, lda, j, k) * AT(A, lda, j, k);
     if (!(s > 0.0)) return j + 1;
     double ljj = sqrt(s);
     AT(A, lda, j, j) = ljj;
+    const int64_t nch = (n - j - 1 + CH - 1) / CH;
 #pragma omp parallel for schedule(static) if (n - j > 512)
-    for (int64_t i = j + 1; i < n; ++i) {
-      double t = AT(A, lda, i, j);
-      for (int64_t k = 0; k < j; ++k) t = t - AT(A, lda, i, k) * AT(A, lda, j, k);
-      AT(A, lda, i, j) = t / ljj;
+    for (int64_t c = 0; c < nch; ++c) {
+      const int64_t i0 = j + 1 + c * CH;
+      const int64_t i1 = i0 + CH < n ? i0 + CH : n;
+      double t[CH];
+      for (int64_t i = i0; i < i1; ++i) t[i - i0] = AT(A, lda, i, j);
+      for (int64_t k = 0; k < j; ++k) {
+        const double ljk = AT(A, lda, j, k);
+        const double* col = &AT(A, lda, 0, k);
+        for (int64_t i = i0; i < i1; ++i) t[i - i0] = t[i - i0] - col[i] * ljk;
+      }
+      for (int64_t i = i0; i < i1; ++i) AT(A, lda, i, j) = t[i - i0] / ljj;
     }
   }
   return 0;

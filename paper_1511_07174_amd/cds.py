@@ -67,6 +67,8 @@ def _declare(L):
         "cds_set_option": [P, ctypes.c_int, I64],
         "cds_tune_set": [P, ctypes.c_int, ctypes.c_int, I64, I64],
         "cds_tune_clear": [P],
+        "cds_tune": [P, ctypes.c_char_p],
+        "cds_tune_check": [ctypes.c_char_p, ctypes.POINTER(I64)],
         "cds_device_error": [P, ctypes.POINTER(I32)],
         "cds_getrf_bufferSize": [P, ctypes.c_int, I64, I64, PSZ],
         "cds_getrs_bufferSize": [P, ctypes.c_int, I64, I64, I64, PSZ],
@@ -107,7 +109,7 @@ def _declare(L):
 
 EXPORTED = [
     "cds_create", "cds_destroy", "cds_set_stream", "cds_get_stream", "cds_set_workspace", "cds_set_option",
-    "cds_tune_set", "cds_tune_clear", "cds_device_error", "cds_status_string",
+    "cds_tune_set", "cds_tune_clear", "cds_tune", "cds_tune_check", "cds_device_error", "cds_status_string",
     "cds_getrf_bufferSize", "cds_getrs_bufferSize", "cds_potrf_bufferSize", "cds_potrs_bufferSize",
     "cds_gesv_mixed_bufferSize", "cds_posv_mixed_bufferSize", "cds_posv_mixed_vbatched_bufferSize",
     "cds_dgetrf", "cds_sgetrf", "cds_dgetrf_strided_batched", "cds_sgetrf_strided_batched",
@@ -216,6 +218,10 @@ class Handle:
 
     def tune_clear(self):
         check(lib().cds_tune_clear(self.h), "cds_tune_clear")
+
+    def tune(self, path: str):
+        """Install the autotuner's JSON table (parsed by the library, cds_tune)."""
+        check(lib().cds_tune(self.h, os.fsencode(path)), "cds_tune")
 
     def kernel_timing(self, kc: str):
         """(launches, ms, flops, bytes) summed over the recorded launches of a kernel class."""
@@ -369,5 +375,5 @@ def handle() -> Handle:
         from . import tune
         path = tune.default_table_path()
         if path.lower() != "none" and os.path.exists(path):
-            tune.load_table(path, _default_handle)
+            _default_handle.tune(path)
     return _default_handle

@@ -8,6 +8,7 @@
 #include "kernels.hpp"
 #include "mixed.hpp"
 #include "solve.hpp"
+#include "tune_table.hpp"
 #include "vbatched.hpp"
 
 namespace {
@@ -162,6 +163,7 @@ cds_status_t potrs_generic(cds_handle_t h, cds_fill_t fill, int64_t n, int64_t n
   return cds::potrs_run<T>(c, (int)n, (int)nrhs, L, lda, B, ldb, h->ws, h->ws_bytes);
 }
 
+bool bad_tune_entry(int key, int dtype, int64_t n_max, int64_t value);
 bool bad_prec(cds_prec_t p) { return p != CDS_PREC_FP32 && p != CDS_PREC_BF16 && p != CDS_PREC_FP16; }
 
 }  // namespace
@@ -268,14 +270,56 @@ cds_status_t cds_set_option(cds_handle_t h, cds_option_t opt, int64_t v) {
 
 cds_status_t cds_tune_set(cds_handle_t h, cds_tune_key_t key, cds_dtype_t dtype, int64_t n_max, int64_t value) {
   if (!h) return CDS_NOT_INITIALIZED;
-  if (key < CDS_TUNE_GETRF_NB || key > CDS_TUNE_VBATCH_TILE) return CDS_INVALID_VALUE;
-  if (dtype != CDS_R_64F && dtype != CDS_R_32F) return CDS_INVALID_VALUE;
-  if (n_max < 0 || value <= 0 || value > 512) return CDS_INVALID_VALUE;
-  if (key == CDS_TUNE_VBATCH_TILE && value != 32 && value != 64) return CDS_INVALID_VALUE;
+  if (bad_tune_entry(key, dtype, n_max, value)) return CDS_INVALID_VALUE;
   for (auto& e : h->tune)
     if (e.key == key && e.dtype == dtype && e.n_max == n_max) { e.value = value; return CDS_SUCCESS; }
   h->tune.push_back(TuneEntry{key, dtype, n_max, value});
   return CDS_SUCCESS;
+}
+
+namespace {
+// The checks cds_tune_set applies to one entry.
+bool bad_tune_entry(int key, int dtype, int64_t n_max, int64_t value) {
+  if (key < CDS_TUNE_GETRF_NB || key > CDS_TUNE_VBATCH_TILE) return true;
+  if (dtype != CDS_R_64F && dtype != CDS_R_32F) return true;
+  if (n_max < 0 || value <= 0 || value > 512) return true;
+  if (key == CDS_TUNE_VBATCH_TILE && value != 32 && value != 64) return true;
+  return false;
+}
+// Reads and validates a table file; arch must name gfx950 when the table names one.
+cds_status_t load_tune_file(const char* path, std::vector<cds::TuneRecord>& recs) {
+  if (!path) return CDS_INVALID_VALUE;
+  std::string arch, err;
+  if (cds::read_tune_table(path, recs, arch, err) != 0) return CDS_INVALID_VALUE;
+  if (!arch.empty() && arch.compare(0, 6, "gfx950") != 0) return CDS_ARCH_MISMATCH;
+  for (const auto& r : recs)
+    if (bad_tune_entry(r.key, r.dtype, r.n_max, r.value)) return CDS_INVALID_VALUE;
+  return CDS_SUCCESS;
+}
+}  // namespace
+
+cds_status_t cds_tune(cds_handle_t h, const char* table_path) {
+  if (!h) return CDS_NOT_INITIALIZED;
+  std::vector<cds::TuneRecord> recs;
+  cds_status_t st = load_tune_file(table_path, recs);
+  if (st != CDS_SUCCESS) return st;   // the handle's table is left as it was
+  h->tune.clear();
+  for (const auto& r : recs) {
+    bool found = false;
+    for (auto& e : h->tune)
+      if (e.key == r.key && e.dtype == r.dtype && e.n_max == r.n_max) { e.value = r.value; found = true; }
+    if (!found) h->tune.push_back(TuneEntry{r.key, r.dtype, r.n_max, r.value});
+  }
+  return CDS_SUCCESS;
+}
+
+cds_status_t cds_tune_check(const char* table_path, int64_t* h_entries) {
+  if (!h_entries) return CDS_INVALID_VALUE;
+  *h_entries = 0;
+  std::vector<cds::TuneRecord> recs;
+  cds_status_t st = load_tune_file(table_path, recs);
+  if (st == CDS_SUCCESS) *h_entries = (int64_t)recs.size();
+  return st;
 }
 
 cds_status_t cds_tune_clear(cds_handle_t h) {

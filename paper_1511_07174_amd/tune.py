@@ -2,7 +2,7 @@
 
 Times candidate settings on the device, keeps the fastest per size bucket and
 persists a JSON table; ``load_table`` installs a table into a handle through
-``cds_tune_set``.  Tuned quantities:
+``cds_tune`` (the library reads the file).  Tuned quantities:
 
 * ``getrf_nb`` (per dtype, per n bucket): block size of the blocked LU, from
   {128, 192, 256, 384};
@@ -166,14 +166,12 @@ def save_table(path, entries, timings=None):
 
 
 def load_table(path, handle=None):
-    """Install a saved table into a handle (default: the package's handle)."""
+    """Install a saved table into a handle (default: the package's handle); the library parses the
+    file (cds_tune)."""
     h = handle or cds.handle()
+    h.tune(path)
     with open(path) as f:
-        table = json.load(f)
-    h.tune_clear()
-    for e in table["entries"]:
-        h.tune_set(KEYS[e["key"]], DTYPES[e["dtype"]], int(e["n_max"]), int(e["value"]))
-    return table
+        return json.load(f)
 
 
 def default_table_path():

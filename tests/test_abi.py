@@ -87,3 +87,46 @@ def test_colmajor_always_copies():
     assert g.data_ptr() != f.data_ptr()
     g[0, 0] = 99.0
     assert f[0, 0] == 0.0
+
+
+def _tune_check(lib, path):
+    lib.cds_tune_check.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]
+    lib.cds_tune_check.restype = ctypes.c_int
+    n = ctypes.c_int64(-1)
+    st = lib.cds_tune_check(os.fsencode(str(path)), ctypes.byref(n))
+    return st, n.value
+
+
+def test_tune_table_reader(lib, tmp_path):
+    """cds_tune's file reader (host only): the shipped table parses; malformed files, unknown keys,
+    values cds_tune_set would refuse and tables of another device are rejected."""
+    import json
+    shipped = os.path.join(ROOT, "paper_1511_07174_amd", "tune_gfx950.json")
+    st, n = _tune_check(lib, shipped)
+    assert st == 0 and n == len(json.load(open(shipped))["entries"])
+    good = {"arch": "gfx950:sramecc+:xnack-", "note": "x \"quoted\" \\u00e9",
+            "entries": [{"key": "getrf_nb", "dtype": "f64", "n_max": 8192, "value": 256},
+                        {"key": "vbatch_tile", "dtype": "f32", "n_max": 1024, "value": 32, "extra": [1, {"a": None}]}],
+            "timings": [{"ms": 1.5e-3, "ok": True}]}
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps(good))
+    assert _tune_check(lib, p) == (0, 2)
+    cases = [
+        ({**good, "arch": "gfx942"}, 4),                                       # another device
+        ({**good, "entries": [{"key": "getrf_nb", "dtype": "f64", "n_max": 8, "value": 1000}]}, 1),
+        ({**good, "entries": [{"key": "vbatch_tile", "dtype": "f32", "n_max": 8, "value": 48}]}, 1),
+        ({**good, "entries": [{"key": "nb", "dtype": "f64", "n_max": 8, "value": 128}]}, 1),
+        ({**good, "entries": [{"key": "getrf_nb", "dtype": "f16", "n_max": 8, "value": 128}]}, 1),
+        ({**good, "entries": [{"key": "getrf_nb", "dtype": "f64", "n_max": 8.5, "value": 128}]}, 1),
+        ({**good, "entries": [{"key": "getrf_nb", "dtype": "f64", "value": 128}]}, 1),
+        ({"arch": "gfx950"}, 1),                                               # no entries
+    ]
+    for table, status in cases:
+        p.write_text(json.dumps(table))
+        assert _tune_check(lib, p)[0] == status, table
+    for text in ['{"entries": [', '[]', '{"entries": []} x', '{"entries": [{"key": "getrf_nb",}]}', '']:
+        p.write_text(text)
+        assert _tune_check(lib, p)[0] == 1, text
+    p.write_text('{"entries": []}')
+    assert _tune_check(lib, p) == (0, 0)
+    assert _tune_check(lib, tmp_path / "missing.json")[0] == 1

@@ -467,3 +467,44 @@ def test_first_pivot_mismatch_reads_the_tie():
     alt[0] = 3                                                   # row 2 has |0.5|: no tie
     k, mult = oracle.first_pivot_mismatch(alt, LU, ipiv)
     assert k == 0 and mult == 0.5
+
+
+def test_freivalds_llt_flags_planted_mistakes():
+    """Zero (to rounding) on the exact Pascal factor; far above the bar for a wrong entry, a transposed
+    factor or a matrix whose upper triangle differs from its lower one (only the lower one is read)."""
+    n = 24
+    P = synth.pascal(n)
+    Lp = synth.pascal_factor(n)
+    assert oracle.freivalds_llt(P, Lp) <= 8 * oracle.EPS
+    assert oracle.freivalds_llt(P, Lp.T.copy()) > 1e-3
+    Pu = P.copy()
+    Pu[0, n - 1] = 1e6                       # upper triangle ignored: still exact
+    assert oracle.freivalds_llt(Pu, Lp) <= 8 * oracle.EPS
+    S = synth.spd_matrix(200, 3)
+    L, info = oracle.potrf(S)
+    assert oracle.freivalds_llt(S, L) <= 1e-14
+    bad = L.copy()
+    bad[150, 30] += 1e-3                     # one wrong entry of L
+    assert oracle.freivalds_llt(S, bad) > 1e-5
+    bad = L.copy()
+    bad[99, 99] *= 1.0 + 2.0 ** -20          # a diagonal entry off by a few parts per million
+    assert oracle.freivalds_llt(S, bad) > 1e-8
+
+
+def test_householder_inverse_and_condition():
+    """The dense closed-form inverse inverts the stored matrix to rounding, its 2-norm condition is kappa,
+    and the closed-form solution differs from the oracle's refined solve of the stored matrix by less
+    than kappa_inf (eta + u): the bound the full-size forward-error checks use."""
+    u = 2.0 ** -53
+    for kappa in (1e2, 1e6):
+        A, x_true, b, meta = synth.householder_system(512, kappa, seed=synth.householder_seed(8192, kappa))
+        M = oracle.householder_inverse(meta["vs_left"], meta["vs_right"], meta["sigma"])
+        assert np.max(np.abs(A @ M - np.eye(512))) <= kappa * 1e-13
+        s = np.linalg.svd(M, compute_uv=False)
+        assert abs(s[0] - kappa) <= 1e-8 * kappa and abs(s[-1] - 1.0) <= 1e-8
+        kinf = oracle.norm_inf(A) * oracle.norm_inf(M)
+        xs = oracle.householder_solve(meta["vs_left"], meta["vs_right"], meta["sigma"], b)
+        xr = oracle.solve_refined(A, b)
+        eta = oracle.eta_inf(A, xr, b)
+        assert np.max(np.abs(xs - xr)) / np.max(np.abs(xr)) <= kinf * (eta + u)
+        assert np.max(np.abs(M @ b - xs)) <= kinf * 4 * u * np.max(np.abs(xs))
