@@ -241,6 +241,22 @@ cds_status_t cds_dgesv_mixed_strided_batched(cds_handle_t handle, cds_prec_t pre
                                              int64_t ldb, int64_t strideB, double* X, int64_t ldx, int64_t strideX,
                                              float* LUlo, int64_t strideLU, int32_t* ipiv, int64_t strideP,
                                              const cds_ir_params_t* params, cds_ir_result_t* results, int64_t batch);
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): cds_dgesv_mixed with
+ * the same arguments and results, but its scratch is a fixed 32 MiB device
+ * array inside the library (one per GPU, held until the process ends) instead
+ * of the handle's workspace; no workspace need be set.  The call allocates
+ * nothing.  Limits: the scratch must hold what cds_gesv_mixed_bufferSize
+ * reports for (prec, n, nrhs, batch 1) with params->fallback = 0, which covers
+ * n <= 32768 with nrhs <= 32; larger sizes return CDS_WORKSPACE_TOO_SMALL and
+ * fallback = 1 returns CDS_UNSUPPORTED, both before anything is enqueued.
+ * Every call on one GPU shares that GPU's scratch: calls that overlap in time
+ * on one GPU (other streams, other handles, other threads) race and must be
+ * ordered by the caller.  A timed-out bounded wait is reported by
+ * cds_device_error on the calling handle. */
+cds_status_t cds_dgesv_mixed_noalloc(cds_handle_t handle, cds_prec_t prec, int64_t n, int64_t nrhs, const double* A,
+                                     int64_t lda, const double* B, int64_t ldb, double* X, int64_t ldx, float* LUlo,
+                                     int32_t* ipiv, const cds_ir_params_t* params, cds_ir_result_t* result);
 /* Refinement only, from existing low-precision LU factors (e.g. for the
  * transposed solve of a gradient): op(A) X = B, op = N or T.  Workspace: the
  * size cds_gesv_mixed_bufferSize reports for CDS_PREC_FP32, the same n, nrhs

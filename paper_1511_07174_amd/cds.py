@@ -89,6 +89,7 @@ def _declare(L):
         "cds_dpotrs": [P, ctypes.c_int, I64, I64, P, I64, P, I64],
         "cds_spotrs": [P, ctypes.c_int, I64, I64, P, I64, P, I64],
         "cds_dgesv_mixed": [P, ctypes.c_int, I64, I64, P, I64, P, I64, P, I64, P, P, P, P],
+        "cds_dgesv_mixed_noalloc": [P, ctypes.c_int, I64, I64, P, I64, P, I64, P, I64, P, P, P, P],
         "cds_dgesv_mixed_strided_batched": [P, ctypes.c_int, I64, I64, P, I64, I64, P, I64, I64, P, I64, I64, P, I64,
                                             P, I64, P, P, I64],
         "cds_dgetrs_mixed_strided_batched": [P, ctypes.c_int, I64, I64, P, I64, I64, P, I64, P, I64, P, I64, I64, P,
@@ -115,7 +116,7 @@ EXPORTED = [
     "cds_dgetrf", "cds_sgetrf", "cds_dgetrf_strided_batched", "cds_sgetrf_strided_batched",
     "cds_dgetrs", "cds_sgetrs", "cds_dgetrs_strided_batched",
     "cds_dpotrf", "cds_spotrf", "cds_dpotrs", "cds_spotrs",
-    "cds_dgesv_mixed", "cds_dgesv_mixed_strided_batched", "cds_dgetrs_mixed_strided_batched",
+    "cds_dgesv_mixed", "cds_dgesv_mixed_noalloc", "cds_dgesv_mixed_strided_batched", "cds_dgetrs_mixed_strided_batched",
     "cds_dposv_mixed", "cds_dposv_mixed_vbatched", "cds_douter_strided_batched",
     "cds_kernel_timing", "cds_kernel_timing_reset",
 ]
@@ -308,6 +309,19 @@ class Handle:
             self.h, PREC[precision], n, nrhs, _p(A), _ld(A), _bstride(A), _p(B), ldb, _bstride(B), _p(X), ldx,
             _bstride(X), _p(LUlo), LUlo.stride(0) if batched else n * n, _p(ipiv), ipiv.stride(0) if batched else n,
             ctypes.byref(prm), _p(results), batch), "gesv_mixed")
+
+    def gesv_mixed_noalloc(self, A, B, X, LUlo, ipiv, result, precision="fp32", params: IrParams | None = None):
+        """cds_dgesv_mixed_noalloc: one system, the library's fixed scratch instead of a workspace
+        (binds torch's current stream only)."""
+        n = A.shape[-1]
+        nrhs = B.shape[-1] if B.dim() == 2 else 1
+        prm = params or default_params()
+        stream = torch.cuda.current_stream(A.device)
+        check(lib().cds_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)), "cds_set_stream")
+        ldb = _ld(B) if B.dim() == 2 else n
+        ldx = _ld(X) if X.dim() == 2 else n
+        check(lib().cds_dgesv_mixed_noalloc(self.h, PREC[precision], n, nrhs, _p(A), _ld(A), _p(B), ldb, _p(X), ldx,
+                                            _p(LUlo), _p(ipiv), ctypes.byref(prm), _p(result)), "gesv_mixed_noalloc")
 
     def getrs_mixed(self, A, LUlo, ipiv, B, X, results, trans=False, params: IrParams | None = None):
         batched = A.dim() == 3

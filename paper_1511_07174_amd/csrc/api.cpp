@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <string.h>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 #include "kernels.hpp"
 #include "mixed.hpp"
@@ -29,6 +30,7 @@ struct cds_handle_s {
   int nb_override = 0, lookahead = 1, leaf = 0, panel_wgs = 0, timing = 0;
   std::vector<TuneEntry> tune;
   cds::KTimer timer;
+  void* noalloc_err = nullptr;   // error word of the fixed scratch, once a no-allocation call has used it
 };
 
 namespace {
@@ -99,6 +101,34 @@ cds_status_t need_ws(const cds_handle_s* h, size_t bytes) {
   return CDS_SUCCESS;
 }
 
+// Fixed device scratch for the no-allocation entry point.  Every GPU that loads
+// the library holds its own copy until the process ends.  Host code never uses
+// the array's name as an address: the device address is resolved once per
+// device with hipGetSymbolAddress (that device current) and kept in
+// g_scratch_addr.
+constexpr size_t kNoallocScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_addr;   // indexed by device ordinal; nullptr = not resolved yet
+
+// Device address of `scratch` on device `dev`, which must be the current device.
+hipError_t scratch_address(int dev, void** out) {
+  *out = nullptr;
+  if (dev < 0) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((size_t)dev >= g_scratch_addr.size()) g_scratch_addr.resize((size_t)dev + 1, nullptr);
+  if (g_scratch_addr[dev] == nullptr) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (ptr == nullptr) return hipErrorInvalidSymbol;
+    g_scratch_addr[dev] = ptr;
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
+}
+
 template <typename T>
 cds_status_t getrf_generic(cds_handle_t h, int64_t n, T* A, int64_t lda, int64_t strideA, int32_t* ipiv,
                            int64_t strideP, int32_t* info, int64_t batch) {
@@ -166,6 +196,31 @@ cds_status_t potrs_generic(cds_handle_t h, cds_fill_t fill, int64_t n, int64_t n
 bool bad_tune_entry(int key, int dtype, int64_t n_max, int64_t value);
 bool bad_prec(cds_prec_t p) { return p != CDS_PREC_FP32 && p != CDS_PREC_BF16 && p != CDS_PREC_FP16; }
 
+// Argument checks of the mixed LU solvers; *nothing = true for a valid call with no work.
+cds_status_t gesv_mixed_args(cds_prec_t prec, int64_t n, int64_t nrhs, const double* A, int64_t lda, int64_t strideA,
+                             const double* B, int64_t ldb, int64_t strideB, const double* X, int64_t ldx,
+                             int64_t strideX, const float* LUlo, int64_t strideLU, const int32_t* ipiv,
+                             int64_t strideP, const cds_ir_params_t& p, const cds_ir_result_t* results,
+                             int64_t batch, bool* nothing) {
+  *nothing = false;
+  if (bad_prec(prec) || bad_dim(n) || nrhs < 0 || nrhs > 2048 || batch < 0) return CDS_INVALID_VALUE;
+  if (bad_ld(lda, n) || bad_ld(ldb, n) || bad_ld(ldx, n)) return CDS_INVALID_VALUE;
+  if (bad_params(p)) return CDS_INVALID_VALUE;
+  if (batch == 0 || n == 0 || nrhs == 0) {
+    *nothing = true;
+    return CDS_SUCCESS;
+  }
+  if (!A || !B || !X || !LUlo || !ipiv || !results) return CDS_INVALID_VALUE;
+  if (batch > 1 && (strideA < lda * n || strideB < ldb * nrhs || strideX < ldx * nrhs || strideLU < n * n ||
+                    strideP < n))
+    return CDS_INVALID_VALUE;
+  if (misaligned(A, 8) || misaligned(B, 8) || misaligned(X, 8) || misaligned(LUlo, 4) || misaligned(ipiv, 4) ||
+      misaligned(results, 8))
+    return CDS_INVALID_VALUE;
+  return CDS_SUCCESS;
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -192,6 +247,12 @@ cds_status_t cds_create(cds_handle_t* out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return CDS_HIP_ERROR;
   if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return CDS_ARCH_MISMATCH;
+  // set-up of the no-allocation entry point's scratch on this device (a failure here is
+  // reported by that entry point, which resolves the address again on its first call)
+  {
+    void* sp = nullptr;
+    (void)scratch_address(dev, &sp);
+  }
   cds_handle_s* h = new cds_handle_s();
   if (hipStreamCreateWithFlags(&h->s1, hipStreamNonBlocking) != hipSuccess) {
     delete h;
@@ -332,14 +393,18 @@ cds_status_t cds_device_error(cds_handle_t h, int32_t* h_err) {
   if (!h) return CDS_NOT_INITIALIZED;
   if (!h_err) return CDS_INVALID_VALUE;
   *h_err = 0;
-  if (!h->ws) return CDS_SUCCESS;
+  void* words[2] = {h->ws, h->noalloc_err};
+  if (!words[0] && !words[1]) return CDS_SUCCESS;
   if (hipStreamSynchronize(h->stream) != hipSuccess) return CDS_HIP_ERROR;
-  int32_t v = 0;
-  if (hipMemcpy(&v, h->ws, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return CDS_HIP_ERROR;
-  *h_err = v;
-  if (v != 0) {
-    if (cds::launch_fill_zero(h->ws, cds::kErrRegion, h->stream) != hipSuccess) return CDS_HIP_ERROR;
-    if (hipStreamSynchronize(h->stream) != hipSuccess) return CDS_HIP_ERROR;
+  for (void* w : words) {
+    if (!w) continue;
+    int32_t v = 0;
+    if (hipMemcpy(&v, w, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return CDS_HIP_ERROR;
+    if (v != 0) {
+      if (*h_err == 0) *h_err = v;
+      if (cds::launch_fill_zero(w, cds::kErrRegion, h->stream) != hipSuccess) return CDS_HIP_ERROR;
+      if (hipStreamSynchronize(h->stream) != hipSuccess) return CDS_HIP_ERROR;
+    }
   }
   return CDS_SUCCESS;
 }
@@ -481,18 +546,11 @@ cds_status_t cds_dgesv_mixed_strided_batched(cds_handle_t h, cds_prec_t prec, in
                                              const cds_ir_params_t* params, cds_ir_result_t* results,
                                              int64_t batch) {
   if (!h) return CDS_NOT_INITIALIZED;
-  if (bad_prec(prec) || bad_dim(n) || nrhs < 0 || nrhs > 2048 || batch < 0) return CDS_INVALID_VALUE;
-  if (bad_ld(lda, n) || bad_ld(ldb, n) || bad_ld(ldx, n)) return CDS_INVALID_VALUE;
   const cds_ir_params_t p = params ? *params : default_params();
-  if (bad_params(p)) return CDS_INVALID_VALUE;
-  if (batch == 0 || n == 0 || nrhs == 0) return CDS_SUCCESS;
-  if (!A || !B || !X || !LUlo || !ipiv || !results) return CDS_INVALID_VALUE;
-  if (batch > 1 && (strideA < lda * n || strideB < ldb * nrhs || strideX < ldx * nrhs || strideLU < n * n ||
-                    strideP < n))
-    return CDS_INVALID_VALUE;
-  if (misaligned(A, 8) || misaligned(B, 8) || misaligned(X, 8) || misaligned(LUlo, 4) || misaligned(ipiv, 4) ||
-      misaligned(results, 8))
-    return CDS_INVALID_VALUE;
+  bool nothing = false;
+  cds_status_t vst = gesv_mixed_args(prec, n, nrhs, A, lda, strideA, B, ldb, strideB, X, ldx, strideX, LUlo,
+                                     strideLU, ipiv, strideP, p, results, batch, &nothing);
+  if (vst != CDS_SUCCESS || nothing) return vst;
   const int nb = resolved_nb(getrf_nb(h, CDS_R_32F, n), n);
   cds_status_t st = need_ws(h, cds::ir_ws_bytes((int)n, (int)nrhs, (int)batch, nb, 0, p.fallback));
   if (st != CDS_SUCCESS) return st;
@@ -506,6 +564,33 @@ cds_status_t cds_dgesv_mixed(cds_handle_t h, cds_prec_t prec, int64_t n, int64_t
                              const cds_ir_params_t* params, cds_ir_result_t* result) {
   return cds_dgesv_mixed_strided_batched(h, prec, n, nrhs, A, lda, 0, B, ldb, 0, X, ldx, 0, LUlo, 0, ipiv, 0, params,
                                          result, 1);
+}
+
+cds_status_t cds_dgesv_mixed_noalloc(cds_handle_t h, cds_prec_t prec, int64_t n, int64_t nrhs, const double* A,
+                                     int64_t lda, const double* B, int64_t ldb, double* X, int64_t ldx, float* LUlo,
+                                     int32_t* ipiv, const cds_ir_params_t* params, cds_ir_result_t* result) {
+  if (!h) return CDS_NOT_INITIALIZED;
+  const cds_ir_params_t p = params ? *params : default_params();
+  bool nothing = false;
+  cds_status_t vst = gesv_mixed_args(prec, n, nrhs, A, lda, 0, B, ldb, 0, X, ldx, 0, LUlo, 0, ipiv, 0, p, result, 1,
+                                     &nothing);
+  if (vst != CDS_SUCCESS || nothing) return vst;
+  if (p.fallback) return CDS_UNSUPPORTED;   // the FP64 fallback needs an n x n copy of A
+  const int nb = resolved_nb(getrf_nb(h, CDS_R_32F, n), n);
+  if (cds::ir_ws_bytes((int)n, (int)nrhs, 1, nb, 0, 0) > kNoallocScratchBytes) return CDS_WORKSPACE_TOO_SMALL;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return CDS_HIP_ERROR;
+  void* sp = nullptr;
+  if (scratch_address(dev, &sp) != hipSuccess) return CDS_HIP_ERROR;
+  Ctx c = make_ctx(h);
+  c.ws = sp;
+  c.ws_bytes = kNoallocScratchBytes;
+  c.err = (int*)sp;
+  // the error word starts at zero on every call; the rest of the scratch is cleared by the drivers
+  if (cds::launch_fill_zero(sp, cds::kErrRegion, h->stream) != hipSuccess) return CDS_HIP_ERROR;
+  h->noalloc_err = sp;
+  return cds::gesv_mixed_run(c, (int)prec, (int)n, (int)nrhs, A, lda, 0, B, ldb, 0, X, ldx, 0, LUlo, n * n, ipiv, 0, p,
+                             result, 1, nb);
 }
 
 cds_status_t cds_dgetrs_mixed_strided_batched(cds_handle_t h, cds_op_t op, int64_t n, int64_t nrhs, const double* A,
