@@ -18,7 +18,7 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 // ---------------------------------------------------------------------------
 // Device error word (bounded spins that time out record here; never hang).
 // ---------------------------------------------------------------------------
-enum DevErr : int { kErrNone = 0, kErrSpinTimeout = 1 };
+enum DevErr : int { kErrNone = 0, kErrSpinTimeout = 1, kErrNoProgress = 2 };
 
 // ~ several seconds of polling; a correct run never comes close.
 constexpr long long kSpinLimit = 1ll << 23;

@@ -49,6 +49,7 @@ struct VbArgs {
   size_t w_elems;    // floats of the factor region (the inverses follow)
   size_t inv_elems;  // floats of the inverse region (the column sums of the residual follow)
   int* ticket;
+  int* err;          // device error word
   cds_ir_result_t* res;
   uint64_t* t_start; uint64_t* t_end;
   double tol, success_tol;
@@ -706,12 +707,18 @@ __global__ void __launch_bounds__(VNT, WG_PER_CU) vbatched_kernel(VbArgs a) {
   float* W = a.ws + (size_t)blockIdx.x * a.wg_elems;
   float* Winv = W + a.w_elems;
   double* cp = reinterpret_cast<double*>(Winv + a.inv_elems);
-  while (true) {
+  // A workgroup draws at most batch + 1 tickets (the counter only grows); more draws mean the
+  // counter was not reset, and the loop stops with an error instead of running on.
+  for (int draws = 0;; ++draws) {
     if (threadIdx.x == 0) sh.ticket = atomicAdd(a.ticket, 1);
     __syncthreads();
     const int t = sh.ticket;
     __syncthreads();
     if (t >= a.batch) break;
+    if (t < 0 || draws > a.batch) {
+      if (threadIdx.x == 0) atomicExch(a.err, (int)kErrNoProgress);
+      break;
+    }
     const int sys = a.order ? a.order[t] : t;
     if (sys < 0 || sys >= a.batch) continue;
     const int n = a.n[sys];
@@ -771,7 +778,7 @@ cds_status_t vbatched_run(Ctx& c, int batch, int nmax, const int32_t* n, const d
   a.batch = batch; a.nrhs = nrhs; a.nmax = nmax;
   a.n = n; a.A = A; a.lda = lda; a.B = B; a.ldb = ldb; a.X = X; a.ldx = ldx; a.order = order;
   a.ws = ws; a.wg_elems = vb_wg_elems(nmax); a.w_elems = vb_w_elems(nmax); a.inv_elems = vb_inv_elems(nmax);
-  a.ticket = ticket; a.res = res; a.t_start = t_start; a.t_end = t_end;
+  a.ticket = ticket; a.err = c.err; a.res = res; a.t_start = t_start; a.t_end = t_end;
   a.tol = prm.tol; a.success_tol = prm.success_tol; a.max_iter = prm.max_iter;
   a.jw32_max_n = jw32_max_n;
   const int grid = std::max(1, std::min(vbatched_grid(), batch));
