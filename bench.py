@@ -147,6 +147,130 @@ def bench_chol(args):
            "posv_converged": bool(r.converged), "classes": cls, "data": "synthetic, device generator seed 6"})
 
 
+def bench_krylov(args):
+    """Krylov solvers at n = 16384 (FP64): CG on A = M M^T / n + I, BiCG, BiCGSTAB and GMRES(30) on
+    A = I + R / (2 sqrt(n)), R ~ U[-1, 1]; b ~ U[-1, 1]; tol 1e-10.  Time to solution, iterations, and the
+    HBM rate of the products with A (8 n^2 bytes each), against the 8 TB/s peak."""
+    import numpy as np
+    import torch
+    import paper_1511_07174_amd as cds
+    from paper_1511_07174_amd.cds import OPT_KERNEL_TIMING
+    dev = torch.device("cuda", 0)
+    n = args.n
+    g = torch.Generator(device=dev).manual_seed(50)
+    M = torch.rand(n, n, generator=g, dtype=torch.float64, device=dev) * 2 - 1
+    S = cds.colmajor(M @ M.T / n + torch.eye(n, dtype=torch.float64, device=dev))
+    G = cds.colmajor(torch.eye(n, dtype=torch.float64, device=dev) + M / (2.0 * n ** 0.5))
+    del M
+    b = torch.rand(n, generator=g, dtype=torch.float64, device=dev) * 2 - 1
+    h = cds.handle()
+    out = {}
+    for method in ("cg", "bicg", "bicgstab", "gmres"):
+        A = S if method == "cg" else G
+        prm = cds.cds.krylov_params(tol=1e-10, max_iter=500, restart=30, check_every=10)
+        x = torch.zeros_like(b)
+        res = torch.zeros(cds.cds.KRYLOV_RESULT_BYTES, dtype=torch.uint8, device=dev)
+
+        def run():
+            x.zero_()
+            h.krylov(method, A, b, x, res, prm)
+        t, tmin, tmax = _events_time(run, args.steps, args.warmup)
+        r = cds.cds.decode_krylov(res)
+        h.set_option(OPT_KERNEL_TIMING, 1)
+        h.kernel_timing_reset()
+        run()
+        torch.cuda.synchronize()
+        cnt, ms, fl, by = h.kernel_timing("krylov_gemv")
+        h.set_option(OPT_KERNEL_TIMING, 0)
+        true = float(torch.linalg.vector_norm(b - A @ x) / torch.linalg.vector_norm(b))
+        avg = ms / max(cnt, 1)
+        out[method] = {"ms": round(t * 1e3, 3), "iters": r.iters, "converged": r.converged, "relres": r.relres,
+                       "true_relres": true, "products": cnt, "product_avg_us": round(avg * 1e3, 1),
+                       "product_GBps": round(8.0 * n * n / (avg * 1e-3) / 1e9, 1),
+                       "product_frac_of_hbm": round(8.0 * n * n / (avg * 1e-3) / 8e12, 4)}
+        log("%s: %.2f ms, %d iterations, product %.1f us (%.0f GB/s)" % (method, t * 1e3, r.iters, avg * 1e3,
+                                                                       8.0 * n * n / (avg * 1e-3) / 1e9))
+    _line({"metric": "Krylov solve time and product bandwidth", "workload": "krylov", "n": n, "tol": 1e-10,
+           "methods": out, "data": "synthetic, device generator seed 50"})
+
+
+def bench_householder(args):
+    """Mixed precision + FP64 refinement on A = H1 diag(sigma) H2 (4 + 4 Householder reflectors, sigma
+    geometric from 1 to 1/kappa), x_true ~ U[-1, 1], b = A x_true: n in {8192, 16384, 32768} x kappa in
+    {1e2, 1e4, 1e6} x factorization in {FP32, BF16, FP16}.  Per case: time to solution, refinement steps,
+    eta (double-double residual on the host), forward error against the closed-form solution, fallback.
+    Where classical refinement stops without reaching eta <= 1e-14, GMRES-based refinement is run too."""
+    import numpy as np
+    import torch
+    import oracle
+    import synth
+    import paper_1511_07174_amd as cds
+    from paper_1511_07174_amd.cds import decode_results
+    dev = torch.device("cuda", 0)
+    oracle.build()
+    sizes = [int(v) for v in args.sizes.split(",")]
+    for n in sizes:
+        for kappa in (1e2, 1e4, 1e6):
+            seed = synth.householder_seed(n, kappa)
+            rg = synth.rng(seed)
+            vl = [rg.standard_normal(n) for _ in range(4)]
+            vr = [rg.standard_normal(n) for _ in range(4)]
+            sigma = float(kappa) ** (-np.arange(n, dtype=np.float64) / max(1, n - 1))
+            # the construction of synth.householder_system, on the device
+            A = torch.eye(n, dtype=torch.float64, device=dev)
+            for v in vr:
+                vt = torch.from_numpy(v).to(dev)
+                w = A @ vt
+                A -= torch.outer(w, (2.0 / float(v @ v)) * vt)
+            A *= torch.from_numpy(sigma).to(dev)[:, None]
+            for v in reversed(vl):
+                vt = torch.from_numpy(v).to(dev)
+                w = vt @ A
+                A -= torch.outer((2.0 / float(v @ v)) * vt, w)
+            A = cds.colmajor(A)
+            xt = torch.from_numpy(rg.uniform(-1.0, 1.0, n)).to(dev)
+            b = A @ xt
+            bh = b.cpu().numpy()
+            xs = oracle.householder_solve(vl, vr, sigma, bh)
+            Ah = np.asfortranarray(A.cpu().numpy()) if n <= 16384 else None
+            for prec in ("fp32", "bf16", "fp16"):
+                prm = cds.default_params(tol=1e-14, success_tol=1e-14, host_check=1)
+                X = torch.zeros_like(b)
+                LUlo = torch.empty(n * n, dtype=torch.float32, device=dev)
+                ipiv = torch.zeros(n, dtype=torch.int32, device=dev)
+                res = torch.zeros(cds.cds.IR_RESULT_BYTES, dtype=torch.uint8, device=dev)
+                h = cds.handle()
+                t, _, _ = _events_time(lambda: h.gesv_mixed(A, b, X, LUlo, ipiv, res, precision=prec, params=prm),
+                                       1, 1)
+                r = decode_results(res)[0]
+                x = X.cpu().numpy()
+                line = {"metric": "mixed-precision solve on a Householder matrix", "workload": "householder",
+                        "n": n, "kappa": kappa, "precision": prec, "seed": seed, "ms": round(t * 1e3, 3),
+                        "gflops": round((2.0 / 3.0 * n ** 3 + 2.0 * n * n) / t / 1e9, 1),
+                        "ir_iters": r.iters, "stop_reason": r.stop_reason, "converged": bool(r.converged),
+                        "eta_gpu": r.eta, "fell_back": bool(r.fell_back),
+                        "fwd_err": float(np.max(np.abs(x - xs)) / np.max(np.abs(x)))}
+                if Ah is not None:
+                    line["eta_oracle"] = oracle.eta_inf(Ah, x, bh)
+                if not r.converged:
+                    res2 = torch.zeros(cds.cds.IR_RESULT_BYTES, dtype=torch.uint8, device=dev)
+                    X2 = torch.zeros_like(b)
+                    t2, _, _ = _events_time(lambda: h.gesv_gmres_ir(A, b, X2, LUlo, ipiv, res2, precision=prec,
+                                                                     params=prm), 1, 1)
+                    r2 = decode_results(res2)[0]
+                    x2 = X2.cpu().numpy()
+                    inner = int(res2.cpu()[36:40].view(torch.int32).item())
+                    line["gmres_ir"] = {"ms": round(t2 * 1e3, 3), "corrections": r2.iters, "gmres_iters": inner,
+                                        "converged": bool(r2.converged), "eta_gpu": r2.eta,
+                                        "fwd_err": float(np.max(np.abs(x2 - xs)) / np.max(np.abs(x2)))}
+                    if Ah is not None:
+                        line["gmres_ir"]["eta_oracle"] = oracle.eta_inf(Ah, x2, bh)
+                _line(line)
+                del LUlo
+            del A, Ah
+            torch.cuda.empty_cache()
+
+
 def bench_adjoint(args):
     """Batched differentiable solve: 64 systems of n = 2048, A, b, w ~ U[-1,1]; loss = sum(w x); forward
     (batched getrf + getrs, or FP32 + FP64 refinement) and backward (A^-T w, -bbar x^T) timed apart."""
@@ -333,7 +457,9 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=8192)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--workload", default="lu", choices=["lu", "chol", "adjoint", "vbatched", "kernels", "copy"])
+    ap.add_argument("--workload", default="lu",
+                    choices=["lu", "chol", "adjoint", "vbatched", "kernels", "copy", "krylov", "householder"])
+    ap.add_argument("--sizes", default="8192,16384,32768", help="householder workload: matrix sizes")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the factorization of one "
@@ -341,7 +467,8 @@ def main():
         sys.exit(2)
     if args.workload != "lu":
         {"chol": bench_chol, "adjoint": bench_adjoint, "vbatched": bench_vbatched,
-         "kernels": bench_kernels, "copy": bench_copy}[args.workload](args)
+         "kernels": bench_kernels, "copy": bench_copy, "krylov": bench_krylov,
+         "householder": bench_householder}[args.workload](args)
         return
 
     import numpy as np

@@ -78,7 +78,8 @@ typedef enum {
   CDS_KC_TRSM = 3,       /* U12 / L21 triangular solves of the factorization */
   CDS_KC_TRSV = 4,       /* triangular solves of getrs / potrs */
   CDS_KC_RESIDUAL = 5,   /* FP64 residual of the refinement */
-  CDS_KC_COUNT = 6
+  CDS_KC_KRYLOV_GEMV = 6,/* products with A (or A^T) inside the Krylov solvers */
+  CDS_KC_COUNT = 7
 } cds_kernel_class_t;
 
 /* Keys of the tuning table (cds_tune_set). */
@@ -291,6 +292,61 @@ cds_status_t cds_dposv_mixed_vbatched(cds_handle_t handle, cds_prec_t prec, int6
                                       const int64_t* ldx, int64_t nrhs, const int32_t* order,
                                       const cds_ir_params_t* params, cds_ir_result_t* results,
                                       uint64_t* t_start, uint64_t* t_end);
+
+/* ---------------------------------------------------------------------------
+ * Krylov solvers (Sec. 2, the iterative family): conjugate gradient for SPD A,
+ * BiCG (residuals with A, shadow residuals with A^T, shadow start r0), its
+ * stabilised form BiCGSTAB, and GMRES restarted after `restart` Arnoldi steps
+ * (Gram-Schmidt applied twice per step, Givens rotations for the small
+ * least-squares problem).  FP64 throughout; A is dense n x n column-major
+ * (lda), read only; b (n) read only; x (n) holds the initial guess on entry and
+ * the solution on exit.  The solve stops when the relative residual of the
+ * method's recurrence, ||r||_2 / ||b||_2, is <= params->tol, or after
+ * params->max_iter iterations: one iteration is one product with A (CG,
+ * GMRES), one with A and one with A^T (BiCG), or two with A (BiCGSTAB).  For
+ * GMRES a cycle's end and every restart recompute the true residual.
+ * result (device, 1): iters, converged, breakdown (a zero inner product ended
+ * the recurrence), relres.  Enqueue-only except that the host reads one state
+ * word every params->check_every iterations (and once per GMRES cycle) to stop
+ * enqueueing after convergence; check_every = 0 enqueues the whole budget
+ * (iterations after the stop exit at once).  Workspace: cds_krylov_bufferSize.
+ * ------------------------------------------------------------------------- */
+typedef enum { CDS_KRYLOV_CG = 0, CDS_KRYLOV_BICG = 1, CDS_KRYLOV_BICGSTAB = 2, CDS_KRYLOV_GMRES = 3 } cds_krylov_t;
+typedef struct {
+  double tol;           /* default 1e-10 */
+  int32_t max_iter;     /* default 1000 */
+  int32_t restart;      /* GMRES steps per cycle, 1..128; default 30 */
+  int32_t check_every;  /* default 10 */
+  int32_t reserved;
+} cds_krylov_params_t;
+typedef struct {
+  int32_t iters;
+  int32_t converged;
+  int32_t breakdown;
+  int32_t reserved;
+  double relres;
+} cds_krylov_result_t;
+cds_status_t cds_krylov_bufferSize(cds_handle_t handle, cds_krylov_t method, int64_t n, int32_t restart,
+                                   size_t* bytes);
+cds_status_t cds_dkrylov(cds_handle_t handle, cds_krylov_t method, int64_t n, const double* A, int64_t lda,
+                         const double* b, double* x, const cds_krylov_params_t* params, cds_krylov_result_t* result);
+
+/* GMRES-based iterative refinement for one right-hand side: the factorization
+ * of cds_dgesv_mixed in `prec` (LUlo, ipiv out), x0 from the low-precision
+ * factors, then repeatedly r = b - A x (FP64), A d = r solved by GMRES in FP64
+ * left-preconditioned with the low-precision factors (inner params: tol is the
+ * preconditioned relative residual, default 1e-4; restart; max_iter per
+ * correction), x += d, until eta = ||r||_inf / (||A||_inf ||x||_inf) <=
+ * ir->tol or ir->max_iter corrections.  result (device): iters = corrections,
+ * eta, eta0, converged (eta <= ir->success_tol), stop_reason as for the mixed
+ * solvers, reserved = the total number of GMRES iterations.  The FP64 fallback
+ * is not offered (ir->fallback must be 0).  Workspace:
+ * cds_gesv_gmres_ir_bufferSize. */
+cds_status_t cds_gesv_gmres_ir_bufferSize(cds_handle_t handle, cds_prec_t prec, int64_t n, int32_t restart,
+                                          size_t* bytes);
+cds_status_t cds_dgesv_gmres_ir(cds_handle_t handle, cds_prec_t prec, int64_t n, const double* A, int64_t lda,
+                                const double* b, double* x, float* LUlo, int32_t* ipiv, const cds_ir_params_t* ir,
+                                const cds_krylov_params_t* inner, cds_ir_result_t* result);
 
 /* ---------------------------------------------------------------------------
  * Outer-product update used by the adjoint of the solve (Abar = -bbar x^T):

@@ -7,7 +7,9 @@ library; the first call does, and raises if it has not been built.
 """
 from .cds import (CdsError, Handle, IrParams, IrResult, colmajor, default_params, handle, lib,  # noqa: F401
                   EXPORTED, LIB_PATH)
-from .solvers import (getrf, getrs, potrf, potrs, solve, solve_vbatched, SolveFn, solve_ad)  # noqa: F401
+from .solvers import (getrf, getrs, potrf, potrs, solve, solve_vbatched, SolveFn, solve_ad,  # noqa: F401
+                      krylov_solve, solve_gmres_ir)
 
 __all__ = ["getrf", "getrs", "potrf", "potrs", "solve", "solve_vbatched", "SolveFn", "solve_ad", "Handle",
+           "krylov_solve", "solve_gmres_ir",
            "IrParams", "default_params", "colmajor", "handle", "lib", "CdsError"]

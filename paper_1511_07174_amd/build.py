@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcds.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["api.cpp", "tune_table.cpp", "util.hip", "gemm.hip", "lu.hip", "chol.hip", "trsm.hip", "solve.hip", "mixed.hip", "vbatched.hip"]
+SOURCES = ["api.cpp", "tune_table.cpp", "util.hip", "gemm.hip", "lu.hip", "chol.hip", "trsm.hip", "solve.hip", "mixed.hip", "vbatched.hip", "krylov.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -25,7 +25,7 @@ LOWER = 0
 R_64F, R_32F = 0, 1
 PREC = {"fp32": 0, "bf16": 1, "fp16": 2}
 OPT_NB, OPT_LOOKAHEAD, OPT_LEAF, OPT_PANEL_WGS, OPT_KERNEL_TIMING = 0, 1, 2, 3, 4
-KC = {"update": 0, "panel": 1, "laswp": 2, "trsm": 3, "trsv": 4, "residual": 5}
+KC = {"update": 0, "panel": 1, "laswp": 2, "trsm": 3, "trsv": 4, "residual": 5, "krylov_gemv": 6}
 TUNE_GETRF_NB, TUNE_POTRF_NB, TUNE_VBATCH_TILE = 0, 1, 2
 
 
@@ -39,6 +39,23 @@ class IrParams(ctypes.Structure):
 
 
 IR_RESULT_BYTES = 40   # int32 iters, info, converged, fell_back; double eta, eta0; int32 stop_reason, reserved
+
+KRYLOV = {"cg": 0, "bicg": 1, "bicgstab": 2, "gmres": 3}
+
+
+class KrylovParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+KRYLOV_RESULT_BYTES = 24   # int32 iters, converged, breakdown, reserved; double relres
+
+
+def krylov_params(**kw) -> KrylovParams:
+    p = KrylovParams(1e-10, 1000, 30, 10, 0)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
 
 _lib = None
 
@@ -96,6 +113,10 @@ def _declare(L):
                                              I64, I64, P, P, I64],
         "cds_dposv_mixed": [P, ctypes.c_int, ctypes.c_int, I64, I64, P, I64, P, I64, P, I64, P, P, P],
         "cds_dposv_mixed_vbatched": [P, ctypes.c_int, I64, I64, P, P, P, P, P, P, P, I64, P, P, P, P, P],
+        "cds_krylov_bufferSize": [P, ctypes.c_int, I64, I32, PSZ],
+        "cds_dkrylov": [P, ctypes.c_int, I64, P, I64, P, P, P, P],
+        "cds_gesv_gmres_ir_bufferSize": [P, ctypes.c_int, I64, I32, PSZ],
+        "cds_dgesv_gmres_ir": [P, ctypes.c_int, I64, P, I64, P, P, P, P, P, P, P],
         "cds_douter_strided_batched": [P, I64, I64, I64, D, P, I64, I64, P, I64, I64, P, I64, I64, I64],
         "cds_kernel_timing": [P, I32, ctypes.POINTER(I64), ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D)],
         "cds_kernel_timing_reset": [P],
@@ -118,6 +139,7 @@ EXPORTED = [
     "cds_dpotrf", "cds_spotrf", "cds_dpotrs", "cds_spotrs",
     "cds_dgesv_mixed", "cds_dgesv_mixed_noalloc", "cds_dgesv_mixed_strided_batched", "cds_dgetrs_mixed_strided_batched",
     "cds_dposv_mixed", "cds_dposv_mixed_vbatched", "cds_douter_strided_batched",
+    "cds_krylov_bufferSize", "cds_dkrylov", "cds_gesv_gmres_ir_bufferSize", "cds_dgesv_gmres_ir",
     "cds_kernel_timing", "cds_kernel_timing_reset",
 ]
 
@@ -148,6 +170,20 @@ def _ld(t: torch.Tensor) -> int:
 
 def _bstride(t: torch.Tensor) -> int:
     return t.stride(0) if t.dim() == 3 else 0
+
+
+@dataclass
+class KrylovResult:
+    iters: int
+    converged: bool
+    breakdown: bool
+    relres: float
+
+
+def decode_krylov(buf: torch.Tensor) -> KrylovResult:
+    h = buf.cpu()
+    ints = h[:16].view(torch.int32).tolist()
+    return KrylovResult(ints[0], bool(ints[1]), bool(ints[2]), h[16:24].view(torch.float64).tolist()[0])
 
 
 @dataclass
@@ -354,6 +390,24 @@ class Handle:
                                              _p(B_ptrs), _p(ldb), _p(X_ptrs), _p(ldx), nrhs, _p(order),
                                              ctypes.byref(prm), _p(results), _p(t_start), _p(t_end)),
               "posv_mixed_vbatched")
+
+    # -- Krylov solvers
+    def krylov(self, method: str, A, b, x, result, params: KrylovParams | None = None):
+        """cds_dkrylov: x (initial guess in, solution out)."""
+        n = A.shape[-1]
+        prm = params or krylov_params()
+        self.bind(self._size("cds_krylov_bufferSize", KRYLOV[method], n, prm.restart), A.device)
+        check(lib().cds_dkrylov(self.h, KRYLOV[method], n, _p(A), _ld(A), _p(b), _p(x), ctypes.byref(prm),
+                                _p(result)), "krylov_" + method)
+
+    def gesv_gmres_ir(self, A, b, x, LUlo, ipiv, result, precision="bf16", params: IrParams | None = None,
+                      inner: KrylovParams | None = None):
+        n = A.shape[-1]
+        prm = params or default_params()
+        kp = inner or krylov_params(tol=1e-4, max_iter=60)
+        self.bind(self._size("cds_gesv_gmres_ir_bufferSize", PREC[precision], n, kp.restart), A.device)
+        check(lib().cds_dgesv_gmres_ir(self.h, PREC[precision], n, _p(A), _ld(A), _p(b), _p(x), _p(LUlo), _p(ipiv),
+                                       ctypes.byref(prm), ctypes.byref(kp), _p(result)), "gesv_gmres_ir")
 
     def outer(self, X, Y, C, alpha=-1.0):
         """C = alpha X Y^T (strided batches when 3-D)."""

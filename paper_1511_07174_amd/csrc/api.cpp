@@ -7,6 +7,7 @@
 #include <mutex>
 #include <vector>
 #include "kernels.hpp"
+#include "krylov.hpp"
 #include "mixed.hpp"
 #include "solve.hpp"
 #include "tune_table.hpp"
@@ -221,6 +222,24 @@ cds_status_t gesv_mixed_args(cds_prec_t prec, int64_t n, int64_t nrhs, const dou
 }
 
 
+}  // namespace
+
+// Krylov solver parameters
+namespace {
+cds_krylov_params_t krylov_defaults() {
+  cds_krylov_params_t p;
+  p.tol = 1e-10;
+  p.max_iter = 1000;
+  p.restart = 30;
+  p.check_every = 10;
+  p.reserved = 0;
+  return p;
+}
+bool bad_krylov(const cds_krylov_params_t& p) {
+  return !(p.tol >= 0.0) || p.max_iter < 0 || p.max_iter > (1 << 24) || p.restart < 1 || p.restart > 128 ||
+         p.check_every < 0;
+}
+bool bad_method(int m) { return m < CDS_KRYLOV_CG || m > CDS_KRYLOV_GMRES; }
 }  // namespace
 
 extern "C" {
@@ -672,6 +691,59 @@ cds_status_t cds_dposv_mixed_vbatched(cds_handle_t h, cds_prec_t prec, int64_t b
   Ctx c = make_ctx(h);
   return cds::vbatched_run(c, (int)batch, (int)nmax, n, A, lda, B, ldb, X, ldx, (int)nrhs, order, p, results, t_start,
                            t_end, jw32);
+}
+
+// ------------------------------------------------------------------------- Krylov solvers
+
+cds_status_t cds_krylov_bufferSize(cds_handle_t h, cds_krylov_t method, int64_t n, int32_t restart, size_t* bytes) {
+  if (!h) return CDS_NOT_INITIALIZED;
+  if (!bytes || bad_method(method) || bad_dim(n) || restart < 1 || restart > 128) return CDS_INVALID_VALUE;
+  *bytes = cds::krylov_ws_bytes((int)method, (int)n, restart, 0);
+  return CDS_SUCCESS;
+}
+
+cds_status_t cds_dkrylov(cds_handle_t h, cds_krylov_t method, int64_t n, const double* A, int64_t lda,
+                         const double* b, double* x, const cds_krylov_params_t* params, cds_krylov_result_t* result) {
+  if (!h) return CDS_NOT_INITIALIZED;
+  const cds_krylov_params_t p = params ? *params : krylov_defaults();
+  if (bad_method(method) || bad_dim(n) || bad_ld(lda, n) || bad_krylov(p)) return CDS_INVALID_VALUE;
+  if (n == 0) return CDS_SUCCESS;
+  if (!A || !b || !x || !result) return CDS_INVALID_VALUE;
+  if (misaligned(A, 8) || misaligned(b, 8) || misaligned(x, 8) || misaligned(result, 8)) return CDS_INVALID_VALUE;
+  cds_status_t st = need_ws(h, cds::krylov_ws_bytes((int)method, (int)n, p.restart, 0));
+  if (st != CDS_SUCCESS) return st;
+  Ctx c = make_ctx(h);
+  return cds::krylov_run(c, (int)method, (int)n, A, lda, b, x, p, result, nullptr, nullptr);
+}
+
+cds_status_t cds_gesv_gmres_ir_bufferSize(cds_handle_t h, cds_prec_t prec, int64_t n, int32_t restart, size_t* bytes) {
+  if (!h) return CDS_NOT_INITIALIZED;
+  if (!bytes || bad_prec(prec) || bad_dim(n) || restart < 1 || restart > 128) return CDS_INVALID_VALUE;
+  *bytes = cds::gmres_ir_ws_bytes((int)n, resolved_nb(getrf_nb(h, CDS_R_32F, n), n), restart);
+  return CDS_SUCCESS;
+}
+
+cds_status_t cds_dgesv_gmres_ir(cds_handle_t h, cds_prec_t prec, int64_t n, const double* A, int64_t lda,
+                                const double* b, double* x, float* LUlo, int32_t* ipiv, const cds_ir_params_t* ir,
+                                const cds_krylov_params_t* inner, cds_ir_result_t* result) {
+  if (!h) return CDS_NOT_INITIALIZED;
+  const cds_ir_params_t p = ir ? *ir : default_params();
+  cds_krylov_params_t kp = krylov_defaults();
+  kp.tol = 1e-4;
+  kp.max_iter = 60;
+  if (inner) kp = *inner;
+  if (bad_prec(prec) || bad_dim(n) || bad_ld(lda, n) || bad_params(p) || p.fallback || bad_krylov(kp))
+    return CDS_INVALID_VALUE;
+  if (n == 0) return CDS_SUCCESS;
+  if (!A || !b || !x || !LUlo || !ipiv || !result) return CDS_INVALID_VALUE;
+  if (misaligned(A, 8) || misaligned(b, 8) || misaligned(x, 8) || misaligned(LUlo, 4) || misaligned(ipiv, 4) ||
+      misaligned(result, 8))
+    return CDS_INVALID_VALUE;
+  const int nb = resolved_nb(getrf_nb(h, CDS_R_32F, n), n);
+  cds_status_t st = need_ws(h, cds::gmres_ir_ws_bytes((int)n, nb, kp.restart));
+  if (st != CDS_SUCCESS) return st;
+  Ctx c = make_ctx(h);
+  return cds::gesv_gmres_ir_run(c, (int)prec, (int)n, A, lda, b, x, LUlo, ipiv, p, kp, result, nb);
 }
 
 cds_status_t cds_douter_strided_batched(cds_handle_t h, int64_t m, int64_t n, int64_t k, double alpha,

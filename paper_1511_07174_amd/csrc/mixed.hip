@@ -12,6 +12,7 @@
 #include "kernels.hpp"
 #include "solve.hpp"
 #include "mixed.hpp"
+#include "krylov.hpp"
 #include <algorithm>
 #include <vector>
 
@@ -607,13 +608,29 @@ static bool carve(void* ws, size_t ws_bytes, int n, int nrhs, int batch, int fal
   return true;
 }
 
+// GMRES as the correction solver of the refinement (one system, one right-hand side).
+struct GmresCorr {
+  const cds_krylov_params_t* p;
+  void* kws; size_t kbytes;    // the Krylov solver's workspace
+  double* d;                   // the correction
+  cds_krylov_result_t* kres;   // the last inner solve's result (device)
+};
+
+__global__ void add_vec_kernel(int n, const double* d, double* x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] += d[i];
+}
+__global__ void add_inner_iters_kernel(cds_ir_result_t* res, const cds_krylov_result_t* kres, int reset) {
+  res->reserved = (reset ? 0 : res->reserved) + (kres ? kres->iters : 0);
+}
+
 // The refinement loop on existing low-precision factors: x0 = solve_lo(b), then
-// r = b - op(A) x (FP64), eta, stop test, d = solve_lo(r), x += d (FP64).
+// r = b - op(A) x (FP64), eta, stop test, d = solve_lo(r), x += d (FP64).  With gm,
+// d solves A d = r by GMRES left-preconditioned with the low-precision factors.
 static cds_status_t refine(Ctx& c, const IrWs& w, int trans, int chol, int n, int nrhs, const double* A, int64_t lda,
                            int64_t strideA, const float* LU, int64_t ldlu, int64_t strideLU, const int32_t* perm,
                            int64_t strideQ, const double* B, int64_t ldb, int64_t strideB, double* X, int64_t ldx,
                            int64_t strideX, const cds_ir_params_t& prm, cds_ir_result_t* res, const int32_t* info,
-                           int batch) {
+                           int batch, const GmresCorr* gm = nullptr) {
   hipStream_t s = c.s0;
   const int rblocks = (n + 63) / 64;
   GetrsCore<float, double> g{};
@@ -683,6 +700,24 @@ static cds_status_t refine(Ctx& c, const IrWs& w, int trans, int chol, int n, in
       for (int v : h_active) any = any || v;
       if (!any) break;
     }
+    if (gm) {
+      // the host decides whether another correction is needed (the GMRES solve is host-driven)
+      int act = 0;
+      if (hipMemcpyAsync(&act, w.active, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) return CDS_HIP_ERROR;
+      if (hipStreamSynchronize(s) != hipSuccess) return CDS_HIP_ERROR;
+      if (!act) break;
+      if (launch_fill_zero(gm->d, (size_t)n * 8, s) != hipSuccess) return CDS_HIP_ERROR;
+      Ctx ck = c;
+      ck.ws = gm->kws;
+      ck.ws_bytes = gm->kbytes;
+      st = krylov_run(ck, CDS_KRYLOV_GMRES, n, A, lda, w.R, gm->d, *gm->p, gm->kres, LU, perm);
+      if (st != CDS_SUCCESS) return st;
+      hipLaunchKernelGGL(add_inner_iters_kernel, dim3(1), dim3(1), 0, s, res, (const cds_krylov_result_t*)gm->kres, 0);
+      hipLaunchKernelGGL(add_vec_kernel, dim3(std::min(1024, (n + 255) / 256)), dim3(256), 0, s, n,
+                         (const double*)gm->d, X);
+      if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
+      continue;
+    }
     GetrsCore<float, double> d = g;
     d.B = w.R; d.ldb = n; d.strideB = (int64_t)n * nrhs;
     d.accumulate = 1;
@@ -691,6 +726,47 @@ static cds_status_t refine(Ctx& c, const IrWs& w, int trans, int chol, int n, in
     if (st != CDS_SUCCESS) return st;
   }
   return CDS_SUCCESS;
+}
+
+size_t gmres_ir_ws_bytes(int n, int nb, int restart) {
+  const size_t kr = krylov_ws_bytes(CDS_KRYLOV_GMRES, n, restart, 1);
+  const size_t corr = al256(kr) + al256((size_t)n * 8) + al256(sizeof(cds_krylov_result_t));
+  return ir_ws_bytes(n, 1, 1, nb, 0, 0) + corr;
+}
+
+// GMRES-based refinement: the factorization of gesv_mixed_run, then corrections from GMRES
+// left-preconditioned with the low-precision factors.
+cds_status_t gesv_gmres_ir_run(Ctx& c, int prec, int n, const double* A, int64_t lda, const double* b, double* x,
+                               float* LU, int32_t* ipiv, const cds_ir_params_t& prm, const cds_krylov_params_t& kp,
+                               cds_ir_result_t* res, int nb) {
+  if (n == 0) return CDS_SUCCESS;
+  hipStream_t s = c.s0;
+  const size_t kr = krylov_ws_bytes(CDS_KRYLOV_GMRES, n, kp.restart, 1);
+  const size_t corr = al256(kr) + al256((size_t)n * 8) + al256(sizeof(cds_krylov_result_t));
+  if (c.ws_bytes < corr + kErrRegion) return CDS_WORKSPACE_TOO_SMALL;
+  // the correction solver's regions at the end of the workspace, the refinement's before them
+  char* top = (char*)c.ws + c.ws_bytes - corr;
+  top = (char*)((uintptr_t)top & ~(uintptr_t)255);
+  GmresCorr gm;
+  gm.p = &kp;
+  gm.kws = top;
+  gm.kbytes = kr;
+  gm.d = (double*)(top + al256(kr));
+  gm.kres = (cds_krylov_result_t*)(top + al256(kr) + al256((size_t)n * 8));
+  const size_t lower = (size_t)(top - (char*)c.ws);
+  IrWs w;
+  if (!carve(c.ws, lower, n, 1, 1, 0, w)) return CDS_WORKSPACE_TOO_SMALL;
+  if (launch_fill_zero(w.anorm, 8, s) != hipSuccess) return CDS_HIP_ERROR;
+  hipLaunchKernelGGL(convert_kernel, dim3((n + 63) / 64, 1), dim3(256), 0, s, A, lda, (int64_t)0, LU, (int64_t)n,
+                     (int64_t)0, n, w.anorm);
+  if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
+  Ctx ci = c;
+  ci.ws = w.inner; ci.ws_bytes = w.inner_bytes;
+  cds_status_t st = getrf_run_mode<float>(ci, n, LU, n, 0, ipiv, 0, w.info, 1, nb, prec, w.scale);
+  if (st != CDS_SUCCESS) return st;
+  if (launch_perm(ipiv, 0, n, w.perm, n, w.gmap, 1, s) != hipSuccess) return CDS_HIP_ERROR;
+  hipLaunchKernelGGL(add_inner_iters_kernel, dim3(1), dim3(1), 0, s, res, (const cds_krylov_result_t*)nullptr, 1);
+  return refine(ci, w, 0, 0, n, 1, A, lda, 0, LU, n, 0, w.perm, n, b, n, 0, x, n, 0, prm, res, w.info, 1, &gm);
 }
 
 // FP64 redo of the systems whose refinement did not converge (host decides).

@@ -24,6 +24,11 @@ cds_status_t posv_mixed_run(Ctx& c, int prec, int n, int nrhs, const double* A, 
                             int64_t ldb, double* X, int64_t ldx, float* L, const cds_ir_params_t& prm,
                             cds_ir_result_t* res, int nb);
 
+size_t gmres_ir_ws_bytes(int n, int nb, int restart);
+cds_status_t gesv_gmres_ir_run(Ctx& c, int prec, int n, const double* A, int64_t lda, const double* b, double* x,
+                               float* LU, int32_t* ipiv, const cds_ir_params_t& prm, const cds_krylov_params_t& kp,
+                               cds_ir_result_t* res, int nb);
+
 hipError_t launch_maxabs_exp(const float* B, int64_t ldb, int64_t strideB, int rows, int cols, int* out, int batch,
                              hipStream_t s);
 hipError_t launch_outer(int m, int n, int k, double alpha, const double* X, int64_t ldx, int64_t strideX,

@@ -87,6 +87,33 @@ def solve(A: torch.Tensor, B: torch.Tensor, precision: str = "fp64", params: IrP
     return X, decode_results(res)
 
 
+def krylov_solve(A: torch.Tensor, b: torch.Tensor, method: str = "cg", x0: torch.Tensor | None = None,
+                 params: cds.KrylovParams | None = None):
+    """Krylov solve of A x = b in FP64 ("cg", "bicg", "bicgstab", "gmres"); returns (x, KrylovResult)."""
+    Ac = colmajor(A.to(torch.float64))
+    bc = b.to(torch.float64).contiguous()
+    x = torch.zeros_like(bc) if x0 is None else x0.to(torch.float64).clone()
+    res = torch.zeros(cds.KRYLOV_RESULT_BYTES, dtype=torch.uint8, device=A.device)
+    _h().krylov(method, Ac, bc, x, res, params)
+    return x, cds.decode_krylov(res)
+
+
+def solve_gmres_ir(A: torch.Tensor, b: torch.Tensor, precision: str = "bf16", params: IrParams | None = None,
+                   inner: cds.KrylovParams | None = None):
+    """GMRES-based refinement: low-precision LU, FP64 GMRES corrections preconditioned by it.
+    Returns (x, IrResult, total GMRES iterations)."""
+    Ac = colmajor(A.to(torch.float64))
+    bc = b.to(torch.float64).contiguous()
+    n = A.shape[-1]
+    x = torch.zeros_like(bc)
+    LUlo = torch.empty(n * n, dtype=torch.float32, device=A.device)
+    ipiv = torch.zeros(n, dtype=torch.int32, device=A.device)
+    res = torch.zeros(cds.IR_RESULT_BYTES, dtype=torch.uint8, device=A.device)
+    _h().gesv_gmres_ir(Ac, bc, x, LUlo, ipiv, res, precision=precision, params=params, inner=inner)
+    inner_its = int(res.cpu()[36:40].view(torch.int32).item())
+    return x, decode_results(res)[0], inner_its
+
+
 def solve_vbatched(systems, nrhs: int = 4, params: IrParams | None = None, order=None, device="cuda"):
     """Many SPD systems of uneven size in one persistent launch (FP32 Cholesky, FP64 refinement).
 
