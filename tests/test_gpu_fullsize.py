@@ -201,6 +201,15 @@ def test_householder_8192(cds, kappa):
         else:
             assert prec != "fp32", r
             assert r.stop_reason in (2, 3), r
+            # GMRES-based refinement on the same factor precision reaches the bar
+            xg, rg, inner = cds.solve_gmres_ir(Ad, bd, precision=prec)
+            xg = host(xg)
+            etag = oracle.eta_inf(A, xg, b)
+            ferrg = np.max(np.abs(xg - xs)) / np.max(np.abs(xg))
+            say("   GMRES-IR: %d corrections, %d GMRES iterations, eta(oracle) %.2e fwd %.2e"
+                % (rg.iters, inner, etag, ferrg))
+            assert rg.converged and etag <= 1e-14, rg
+            assert ferrg <= n * kappa * etag * 1.01 + 64 * np.sqrt(n) * 2.0 ** -53
     assert cds.handle().device_error() == 0
 
 
