@@ -314,6 +314,27 @@ __device__ void compact_entries(const int* s_dst, const int* s_src, int ne, int 
   }
 }
 
+// A thread's row of a 32-column leaf, held in registers.  Columns are read and
+// written at compile-time indices in unrolled loops, and at the column step's
+// wave-uniform index through relative register addressing (a short
+// s_set_gpr_idx sequence, not a chain of selects and not scratch memory).
+template <typename T> struct LeafRow;
+template <> struct LeafRow<float> {
+  typedef float vt __attribute__((ext_vector_type(32)));
+  vt a;
+  __device__ __forceinline__ float get(int c) const { return a[c]; }
+  __device__ __forceinline__ void set(int c, float x) { a[c] = x; }
+};
+template <> struct LeafRow<double> {
+  typedef double vt __attribute__((ext_vector_type(16)));
+  vt lo, hi;
+  __device__ __forceinline__ double get(int c) const { return c < 16 ? lo[c] : hi[c - 16]; }
+  __device__ __forceinline__ void set(int c, double x) {
+    if (c < 16) lo[c] = x;
+    else hi[c - 16] = x;
+  }
+};
+
 // The panel: G workgroups of PNT rows.  Per leaf of W columns, each thread
 // keeps its row of the leaf in registers through the column loop; after the
 // leaf, the leaf's interchanges move rows between workgroups in one
@@ -362,27 +383,24 @@ __global__ void __launch_bounds__(PNT, 2) panel_kernel(PanelArgs<T> P) {
     const int wl = min(W, jb - c0);
     const int c1 = c0 + wl;
     const bool act = own && row >= c0;
-    T v[W];
+    LeafRow<T> v;
 #pragma unroll
-    for (int cc = 0; cc < W; ++cc) v[cc] = (act && cc < wl) ? A[row + (size_t)(c0 + cc) * lda] : (T)0;
+    for (int cc = 0; cc < W; ++cc) v.set(cc, (act && cc < wl) ? A[row + (size_t)(c0 + cc) * lda] : (T)0);
     for (int cc = 0; cc < wl; ++cc) {
       const int j = c0 + cc;
       const int par = j & 1;
       const uint32_t flag = (uint32_t)(P.k + j + 1);
-      // v[cc] through selects (a dynamic register index would put v in scratch memory)
-      T x = v[0];
-#pragma unroll
-      for (int c2 = 1; c2 < W; ++c2) x = (c2 == cc) ? v[c2] : x;
+      T x = v.get(cc);
       T wbm;
       int wbr;
       wave_pivot_search<T>(fabs(x), row, own && row >= j, wbm, wbr);
       if (row == wbr) {
 #pragma unroll
-        for (int c2 = 0; c2 < W; ++c2) rowbuf[wave][c2] = v[c2];
+        for (int c2 = 0; c2 < W; ++c2) rowbuf[wave][c2] = v.get(c2);
       }
       if (own && row == j) {
 #pragma unroll
-        for (int c2 = 0; c2 < W; ++c2) jbuf[c2] = v[c2];
+        for (int c2 = 0; c2 < W; ++c2) jbuf[c2] = v.get(c2);
       }
       if (lane == 0) { red_mag[wave] = wbm; red_row[wave] = wbr; }
       __syncthreads();
@@ -394,17 +412,19 @@ __global__ void __launch_bounds__(PNT, 2) panel_kernel(PanelArgs<T> P) {
       const T piv = prow[cc];
       if (own && row == j) {
 #pragma unroll
-        for (int c2 = 0; c2 < W; ++c2) v[c2] = prow[c2];
+        for (int c2 = 0; c2 < W; ++c2) v.set(c2, prow[c2]);
       } else if (own && row == p) {
 #pragma unroll
-        for (int c2 = 0; c2 < W; ++c2) v[c2] = jrow[c2];
+        for (int c2 = 0; c2 < W; ++c2) v.set(c2, jrow[c2]);
         x = jrow[cc];
       }
       if (own && row > j && piv != (T)0) {
-        // prm is zero outside (cc, wl): one unconditional fused update per column
+        // prm is zero outside (cc, wl): one unconditional fused update per column, then the
+        // multiplier into column cc
         const T lmul = x / piv;
 #pragma unroll
-        for (int c2 = 0; c2 < W; ++c2) v[c2] = (c2 == cc) ? lmul : fma(-lmul, prm[c2], v[c2]);
+        for (int c2 = 0; c2 < W; ++c2) v.set(c2, fma(-lmul, prm[c2], v.get(c2)));
+        v.set(cc, lmul);
       }
       if (tid < W) L11[cc][tid] = prow[tid];
       if (tid == 0) {
@@ -417,7 +437,7 @@ __global__ void __launch_bounds__(PNT, 2) panel_kernel(PanelArgs<T> P) {
     if (act) {
 #pragma unroll
       for (int cc = 0; cc < W; ++cc)
-        if (cc < wl) A[row + (size_t)(c0 + cc) * lda] = v[cc];
+        if (cc < wl) A[row + (size_t)(c0 + cc) * lda] = v.get(cc);
     }
     __syncthreads();
     if (wave == 0) {
@@ -479,7 +499,7 @@ __global__ void __launch_bounds__(PNT, 2) panel_kernel(PanelArgs<T> P) {
         T sel = (T)0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const T t = __shfl(v[4 * kc + q], src, kWave);
+          const T t = __shfl(v.get(4 * kc + q), src, kWave);
           sel = ((lane >> 4) == q) ? t : sel;
         }
         bop[rt][kc] = sel;
