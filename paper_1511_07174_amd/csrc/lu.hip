@@ -56,6 +56,13 @@ struct SlotLayout {
   __host__ __device__ int64_t sw(int par, int e) const { return 2 * cs_par() + par * sw_par() + (int64_t)e * jb * LLW; }
 };
 
+// A barrier that orders LDS accesses only: global loads and stores issued before it stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Gather half of a column step for up to 64 workgroups.  Lane i polls
 // workgroup i's header, and lane l < wl value l of row j.  Each poll round also
 // fetches, with one coalesced load per word, the candidate row of the best
@@ -246,44 +253,36 @@ __device__ __forceinline__ void colstep_exchange(uint64_t* slots, const SlotLayo
 
 // Compose the leaf's sequential interchanges (c0+cc <-> piv[cc]) into a list of
 // (dst, src) moves.  Entries 0..wl-1 are the top positions c0..c0+wl-1 (src may
-// equal dst); later entries are the other moved positions.  Wave 0 only; returns
-// the entry count in every lane.
+// equal dst); later entries are the other moved positions (pivot rows below the
+// leaf, each once, in the order of first use).  Every lane traces its position
+// back through the interchanges in reverse order, so there is no serial table
+// update.  Wave 0 only; returns the entry count in every lane.
 template <int W>
 __device__ int compose_leaf(const int* s_piv, int c0, int wl, int* s_dst, int* s_src, int* s_ne) {
   const int lane = lane_id();
-  int mypos = -1, mysrc = -1, cnt = 0;   // lane L holds table entry L (2W <= 64)
+  const int c1 = c0 + wl;
+  const int mypiv = lane < wl ? s_piv[lane] : -1;
+  // lane cc names the pivot row of column cc when it lies below the leaf and no earlier column chose it
+  bool other = mypiv >= c1;
   for (int cc = 0; cc < wl; ++cc) {
-    const int a = c0 + cc, bb = s_piv[cc];
-    if (a == bb) continue;
-    uint64_t ma = __ballot(lane < cnt && mypos == a);
-    uint64_t mb = __ballot(lane < cnt && mypos == bb);
-    int ia = ma ? (__ffsll((unsigned long long)ma) - 1) : -1;
-    int ib = mb ? (__ffsll((unsigned long long)mb) - 1) : -1;
-    int sa = ia >= 0 ? __shfl(mysrc, ia) : a;
-    int sb = ib >= 0 ? __shfl(mysrc, ib) : bb;
-    if (ia < 0) { ia = cnt++; if (lane == ia) mypos = a; }
-    if (ib < 0) { ib = cnt++; if (lane == ib) mypos = bb; }
-    if (lane == ia) mysrc = sb;
-    if (lane == ib) mysrc = sa;
+    const int pc = __builtin_amdgcn_readlane(mypiv, cc);
+    other = other && !(cc < lane && pc == mypiv);
   }
-  // top entries (the loop is uniform: every lane takes part in each shuffle)
-  const int d = c0 + lane;
-  int s = d;
-  for (int e = 0; e < cnt; ++e) {
-    const int pe = __shfl(mypos, e);
-    const int se = __shfl(mysrc, e);
-    if (pe == d) s = se;
+  int src = c0 + lane, osrc = mypiv;
+  for (int cc = wl - 1; cc >= 0; --cc) {
+    const int a = c0 + cc, b = __builtin_amdgcn_readlane(mypiv, cc);
+    src = src == a ? b : (src == b ? a : src);
+    osrc = osrc == a ? b : (osrc == b ? a : osrc);
   }
   if (lane < wl) {
-    s_dst[lane] = d;
-    s_src[lane] = s;
+    s_dst[lane] = c0 + lane;
+    s_src[lane] = src;
   }
-  bool other = lane < cnt && mypos >= c0 + wl;
-  uint64_t mo = __ballot(other);
+  const uint64_t mo = __ballot(other);
   if (other) {
-    int idx = wl + __popcll(mo & ((1ull << lane) - 1ull));
-    s_dst[idx] = mypos;
-    s_src[idx] = mysrc;
+    const int idx = wl + __popcll(mo & ((1ull << lane) - 1ull));
+    s_dst[idx] = mypiv;
+    s_src[idx] = osrc;
   }
   const int ne = wl + __popcll(mo);
   if (lane == 0) *s_ne = ne;
@@ -439,14 +438,16 @@ __global__ void __launch_bounds__(PNT, 2) panel_kernel(PanelArgs<T> P) {
       for (int cc = 0; cc < W; ++cc)
         if (cc < wl) A[row + (size_t)(c0 + cc) * lda] = v.get(cc);
     }
-    __syncthreads();
+    // these two barriers order LDS only (the pivots, L11 and the move lists); nothing reads the
+    // leaf columns just stored before the full barriers further down
+    lds_barrier();
     if (wave == 0) {
       const int ne0 = compose_leaf<W>(s_piv, c0, wl, s_dst, s_src, &s_ne);
       // the lists written by other lanes of this wave are read below: order the LDS accesses
       wave_fence();
       compact_entries(s_dst, s_src, ne0, g, s_own, &s_nown, s_dl, &s_ndl);
     }
-    __syncthreads();
+    lds_barrier();
     if (g == 0 && tid < wl) ipiv[c0 + tid] = P.k + s_piv[tid] + 1;
     const int ne = s_ne;
     const int spar = leafc & 1;
@@ -550,17 +551,18 @@ __global__ void __launch_bounds__(PNT, 2) panel_kernel(PanelArgs<T> P) {
       }
       __syncthreads();
       if (cw == 0) break;
-      // U_right = L11^{-1} P_top, one thread per column
+      // U_right = L11^{-1} P_top, one thread per column, by columns of L11: as soon as u[t] is final
+      // it is taken out of every later row, so each u[i] still subtracts L11[i][t] u[t] in the order
+      // t = 0, 1, ..., i - 1, while the dependent chain is W steps long instead of W^2 / 2
       if (tid < cw) {
         T u[W];
 #pragma unroll
         for (int i = 0; i < W; ++i) u[i] = (i < wl) ? Ubuf[i][tid] : (T)0;
 #pragma unroll
-        for (int i = 1; i < W; ++i) {
-          T acc = u[i];
+        for (int t = 0; t < W - 1; ++t) {
+          const T ut = u[t];
 #pragma unroll
-          for (int t = 0; t < i; ++t) acc -= L11[i][t] * u[t];
-          u[i] = (i < wl) ? acc : (T)0;
+          for (int i = t + 1; i < W; ++i) u[i] = (i < wl) ? u[i] - L11[i][t] * ut : (T)0;
         }
 #pragma unroll
         for (int i = 0; i < W; ++i) Ubuf[i][tid] = u[i];
@@ -574,44 +576,82 @@ __global__ void __launch_bounds__(PNT, 2) panel_kernel(PanelArgs<T> P) {
       }
       // rows >= c1 of this wave: C[rows, cols] -= L21[rows, :] U_right[:, cols] on 16x16x4 MFMA tiles,
       // computed transposed (D = -U^T L21^T) so that a lane's accumulators run down a column.
-      // Sub-chunks of 32 columns.
+      // Tiles of 16 columns.
       {
-        const int nsub = (cw + 31) / 32;
-        for (int sub = 0; sub < nsub; ++sub) {
-          const int xs = x0 + sub * 32;
-          const int cws = min(32, x0 + cw - xs);
-#pragma unroll
-          for (int ct = 0; ct < 2; ++ct) {
-            acc_t acc[4];
-#pragma unroll
-            for (int rt = 0; rt < 4; ++rt)
-#pragma unroll
-              for (int vq = 0; vq < 4; ++vq) {
-                const int ci = ct * 16 + (F64 ? ((lane >> 4) + 4 * vq) : (4 * (lane >> 4) + vq));
-                const int rr = g * PNT + wr + rt * 16 + (lane & 15);
-                const bool ok = rr < m && rr >= c1 && ci < cws;
-                acc[rt][vq] = ok ? A[rr + (size_t)(xs + ci) * lda] : (T)0;
-              }
-#pragma unroll
-            for (int kc = 0; kc < W / 4; ++kc) {
-              const T aop = -Ubuf[4 * kc + (lane >> 4)][xs - x0 + ct * 16 + (lane & 15)];
-#pragma unroll
-              for (int rt = 0; rt < 4; ++rt) {
-                if constexpr (F64)
-                  acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop[rt][kc], acc[rt], 0, 0, 0);
-                else
-                  acc[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop[rt][kc], acc[rt], 0, 0, 0);
-              }
-            }
+        const int ntile = 2 * ((cw + 31) / 32);
+        const int rr0 = g * PNT + wr + (lane & 15);
+        // a tile whose 64 rows all lie in [c1, m) and whose 16 columns all exist takes unmasked loads
+        // and stores (wave-uniform test); the others mask element by element
+        const bool rows_full = g * PNT + wr >= c1 && g * PNT + wr + 63 < m;
+        auto load_c = [&](acc_t (&a)[4], int t) {
+          const int xs = x0 + (t >> 1) * 32, cws = min(32, x0 + cw - xs), ct = t & 1;
+          if (rows_full && ct * 16 + 16 <= cws) {
 #pragma unroll
             for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
               for (int vq = 0; vq < 4; ++vq) {
                 const int ci = ct * 16 + (F64 ? ((lane >> 4) + 4 * vq) : (4 * (lane >> 4) + vq));
-                const int rr = g * PNT + wr + rt * 16 + (lane & 15);
-                if (rr < m && rr >= c1 && ci < cws) A[rr + (size_t)(xs + ci) * lda] = acc[rt][vq];
+                a[rt][vq] = A[rr0 + rt * 16 + (size_t)(xs + ci) * lda];
               }
+            return;
           }
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int vq = 0; vq < 4; ++vq) {
+              const int ci = ct * 16 + (F64 ? ((lane >> 4) + 4 * vq) : (4 * (lane >> 4) + vq));
+              const int rr = rr0 + rt * 16;
+              const bool ok = rr < m && rr >= c1 && ci < cws;
+              a[rt][vq] = ok ? A[rr + (size_t)(xs + ci) * lda] : (T)0;
+            }
+        };
+        auto mfma_store = [&](acc_t (&a)[4], int t) {
+          const int xs = x0 + (t >> 1) * 32, cws = min(32, x0 + cw - xs), ct = t & 1;
+          T aop[W / 4];
+#pragma unroll
+          for (int kc = 0; kc < W / 4; ++kc) aop[kc] = -Ubuf[4 * kc + (lane >> 4)][xs - x0 + ct * 16 + (lane & 15)];
+#pragma unroll
+          for (int kc = 0; kc < W / 4; ++kc) {
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt) {
+              if constexpr (F64)
+                a[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[kc], bop[rt][kc], a[rt], 0, 0, 0);
+              else
+                a[rt] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[kc], bop[rt][kc], a[rt], 0, 0, 0);
+            }
+          }
+          if (rows_full && ct * 16 + 16 <= cws) {
+#pragma unroll
+            for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+              for (int vq = 0; vq < 4; ++vq) {
+                const int ci = ct * 16 + (F64 ? ((lane >> 4) + 4 * vq) : (4 * (lane >> 4) + vq));
+                A[rr0 + rt * 16 + (size_t)(xs + ci) * lda] = a[rt][vq];
+              }
+            return;
+          }
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int vq = 0; vq < 4; ++vq) {
+              const int ci = ct * 16 + (F64 ? ((lane >> 4) + 4 * vq) : (4 * (lane >> 4) + vq));
+              const int rr = rr0 + rt * 16;
+              if (rr < m && rr >= c1 && ci < cws) A[rr + (size_t)(xs + ci) * lda] = a[rt][vq];
+            }
+        };
+        // three tiles of C in flight: a tile's MFMAs take far less time than its loads
+        acc_t b0[4], b1[4], b2[4];
+        if (ntile > 0) load_c(b0, 0);
+        if (ntile > 1) load_c(b1, 1);
+        for (int t = 0; t < ntile; t += 3) {
+          if (t + 2 < ntile) load_c(b2, t + 2);
+          mfma_store(b0, t);
+          if (t + 1 >= ntile) break;
+          if (t + 3 < ntile) load_c(b0, t + 3);
+          mfma_store(b1, t + 1);
+          if (t + 2 >= ntile) break;
+          if (t + 4 < ntile) load_c(b1, t + 4);
+          mfma_store(b2, t + 2);
         }
       }
       __syncthreads();   // Ubuf is reloaded by the next chunk
