@@ -43,7 +43,8 @@ struct KState {
   double beta0;      // GMRES: ||r|| at the cycle start
 };
 
-int nparts(int n) { return std::max(1, std::min(KMAXP, (n + KNT * 4 - 1) / (KNT * 4))); }
+// blocks of the vector kernels (and so the count of each dot product's partials): one row per thread
+int nparts(int n) { return std::max(1, std::min(KMAXP, (n + KNT - 1) / KNT)); }
 int nchunks(int n) { return std::max(1, (n + KCW - 1) / KCW); }
 
 // sum of `np` partials in a fixed order, the same in every block (wave 0 only)
