@@ -244,7 +244,7 @@ cds_status_t cds_dgesv_mixed_strided_batched(cds_handle_t handle, cds_prec_t pre
                                              const cds_ir_params_t* params, cds_ir_result_t* results, int64_t batch);
 /* For callers that cannot allocate device memory (code under graph capture,
  * tight serving loops, harnesses that forbid hipMalloc): cds_dgesv_mixed with
- * the same arguments and results, but its scratch is a fixed 32 MiB device
+ * the same arguments and results, but its scratch is a fixed 72 MiB device
  * array inside the library (one per GPU, held until the process ends) instead
  * of the handle's workspace; no workspace need be set.  The call allocates
  * nothing.  Limits: the scratch must hold what cds_gesv_mixed_bufferSize

@@ -107,7 +107,7 @@ cds_status_t need_ws(const cds_handle_s* h, size_t bytes) {
 // the array's name as an address: the device address is resolved once per
 // device with hipGetSymbolAddress (that device current) and kept in
 // g_scratch_addr.
-constexpr size_t kNoallocScratchBytes = (size_t)32 << 20;
+constexpr size_t kNoallocScratchBytes = (size_t)72 << 20;
 static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
 
 std::mutex g_scratch_mu;

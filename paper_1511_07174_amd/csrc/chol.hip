@@ -276,7 +276,7 @@ size_t potrf_ws_bytes(int n, int nb, size_t elem) {
 }
 
 template <typename T>
-cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int nb, int mode, int* scale_exp) {
+cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int nb, int mode, float* scale_part) {
   hipStream_t s = c.s0;
   if (launch_fill_i32(info, 1, 0, s) != hipSuccess) return CDS_HIP_ERROR;
   if (n == 0) return CDS_SUCCESS;
@@ -307,9 +307,9 @@ cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int
                            1, 1, info, st) != hipSuccess)
         return CDS_HIP_ERROR;
     }
-    if (mode == 2 && scale_exp != nullptr) {
+    if (mode == 2 && scale_part != nullptr) {
       if constexpr (std::is_same<T, float>::value) {
-        if (launch_maxabs_exp(A + (k + jb) + (size_t)k * lda, lda, 0, rem, jb, scale_exp, 1, st) != hipSuccess)
+        if (launch_maxabs_part(A + (k + jb) + (size_t)k * lda, lda, 0, rem, jb, scale_part, 1, st) != hipSuccess)
           return CDS_HIP_ERROR;
       }
     }
@@ -324,9 +324,12 @@ cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int
     g.A = A + r0 + (size_t)k * lda; g.lda = lda; g.strideA = 0;
     g.B = A + c0 + (size_t)k * lda; g.ldb = lda; g.strideB = 0;
     g.C = A + r0 + (size_t)c0 * lda; g.ldc = lda; g.strideC = 0;
-    g.alpha = (T)-1; g.transB = 1; g.lower = 1; g.scale_exp = nullptr;
+    g.alpha = (T)-1; g.transB = 1; g.lower = 1; g.scale_part = nullptr; g.scaleA = 0;
     g.guard = info;
-    if (mode == 2 && scale_exp != nullptr) g.scale_exp = scale_exp;
+    if (mode == 2 && scale_part != nullptr) {
+      g.scale_part = scale_part;
+      g.scaleA = 1;   // A and B are both L21
+    }
     KScope ks(c.timer, CDS_KC_UPDATE, st, (double)m * nn * jb * 2.0 - (double)nn * nn * jb,
               (double)sizeof(T) * ((double)m * nn + (double)(m + nn) * jb));
     return launch_gemm<T>(g, 1, mode, st) == hipSuccess ? CDS_SUCCESS : CDS_HIP_ERROR;
@@ -352,6 +355,6 @@ cds_status_t potrf_run(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int nb) 
 
 template cds_status_t potrf_run<double>(Ctx&, int, double*, int64_t, int32_t*, int);
 template cds_status_t potrf_run<float>(Ctx&, int, float*, int64_t, int32_t*, int);
-template cds_status_t potrf_run_mode<float>(Ctx&, int, float*, int64_t, int32_t*, int, int, int*);
+template cds_status_t potrf_run_mode<float>(Ctx&, int, float*, int64_t, int32_t*, int, int, float*);
 
 }  // namespace cds

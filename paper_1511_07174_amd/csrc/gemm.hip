@@ -299,8 +299,8 @@ gemm_native_kernel(GemmArgs<T> g) {
 
 // ------------------------------------------------------------------------------------
 // Mixed kernel: FP32 data, BF16 (MODE 1) or FP16 (MODE 2) operands, FP32 accumulate.
-// For FP16, op(B) is multiplied by 2^bscale_exp (device value) while staging and the
-// product by 2^-bscale_exp, both exact.
+// For FP16, op(B) is multiplied by 2^e while staging and the product by 2^-e, both
+// exact; e comes from the partial maxima of |op(B)| (one wave reduces them).
 // ------------------------------------------------------------------------------------
 template <int MODE>
 __global__ void __launch_bounds__(NT, 2)
@@ -317,11 +317,20 @@ gemm_mixed_kernel(GemmArgs<float> g) {
   const float* __restrict__ A = g.A + (size_t)b * g.strideA;
   const float* __restrict__ B = g.B + (size_t)b * g.strideB;
   float* __restrict__ C = g.C + (size_t)b * g.strideC;
-  float bscale = 1.0f, unscale = 1.0f;
-  if (MODE == 2 && g.scale_exp != nullptr) {
-    int e = g.scale_exp[b];
+  float bscale = 1.0f, ascale = 1.0f, unscale = 1.0f;
+  static_assert(kScaleParts == 64, "one partial maximum per lane");
+  if (MODE == 2 && g.scale_part != nullptr) {
+    const float t = wave_max(g.scale_part[(size_t)b * kScaleParts + (threadIdx.x & 63)]);
+    const int lim = g.scaleA ? 50 : 100;   // 2^-2e stays a normal FP32 number
+    int e = 0;
+    if (t > 0.f && t == t && t < INFINITY) {
+      int ex;
+      frexpf(t, &ex);   // t in [2^(ex-1), 2^ex)
+      e = max(-lim, min(lim, 14 - ex));
+    }
     bscale = ldexpf(1.0f, e);
-    unscale = ldexpf(1.0f, -e);
+    if (g.scaleA) ascale = bscale;
+    unscale = ldexpf(1.0f, g.scaleA ? -2 * e : -e);
   }
 
   int tiles_m = (g.m + BM - 1) / BM, tiles_n = (g.n + BN - 1) / BN;
@@ -331,8 +340,10 @@ gemm_mixed_kernel(GemmArgs<float> g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave & 1) * 64, wc = (wave >> 1) * 64;
 
-  // each thread stages 2 units of 8 k-values for A and 2 for B
+  // each thread stages 2 units of 8 k-values for A and 2 for B; with B not transposed a unit is 8
+  // consecutive elements of a column, read as two 16-byte vectors where aligned and whole
   float ra[2][8], rb[2][8];
+  const bool bvec = !g.transB && ((uintptr_t)B % 16 == 0) && (g.ldb % 4 == 0);
   auto load_tile = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
@@ -351,6 +362,16 @@ gemm_mixed_kernel(GemmArgs<float> g) {
       int j, kg;
       if (!g.transB) { kg = u % 4; j = u / 4; } else { j = u % BN; kg = u / BN; }
       int gj = col0 + j;
+      if (bvec && gj < g.n && k0 + kg * 8 + 8 <= g.k) {
+        const f4* p = reinterpret_cast<const f4*>(B + (k0 + kg * 8) + (size_t)gj * g.ldb);
+        const f4 v0 = p[0], v1 = p[1];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          rb[r][t] = v0[t];
+          rb[r][4 + t] = v1[t];
+        }
+        continue;
+      }
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         int gk = k0 + kg * 8 + t;
@@ -366,7 +387,7 @@ gemm_mixed_kernel(GemmArgs<float> g) {
       int i = u % BM, kg = u / BM;
       h8_t v;
 #pragma unroll
-      for (int t = 0; t < 8; ++t) v[t] = (h_t)ra[r][t];
+      for (int t = 0; t < 8; ++t) v[t] = (h_t)(ra[r][t] * ascale);
       *reinterpret_cast<h8_t*>(&As[buf][i][kg * 8]) = v;
     }
 #pragma unroll
@@ -411,19 +432,40 @@ gemm_mixed_kernel(GemmArgs<float> g) {
     if (kt + 1 < ktiles) store_tile(buf ^ 1);
     __syncthreads();
   }
+  // epilogue C += alpha (acc 2^-e): a lane's four accumulators of a block are four consecutive rows
+  // of one column, so C moves as one 16-byte access where the group is whole and aligned (every
+  // read is issued before the first write)
+  const bool c_al = ((uintptr_t)C % 16 == 0) && (g.ldc % 4 == 0);
+  f4 cv[4][4];
 #pragma unroll
   for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 4; ++ni)
+    for (int ni = 0; ni < 4; ++ni) {
+      const int gi0 = row0 + wr + mi * 16 + 4 * (lane / 16), gj = col0 + wc + ni * 16 + (lane & 15);
+      if (c_al && gi0 + 3 < g.m && gj < g.n && (!g.lower || gi0 >= gj))
+        cv[mi][ni] = *reinterpret_cast<const f4*>(C + gi0 + (size_t)gj * g.ldc);
+    }
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni) {
+      const int gi0 = row0 + wr + mi * 16 + 4 * (lane / 16), gj = col0 + wc + ni * 16 + (lane & 15);
+      if (c_al && gi0 + 3 < g.m && gj < g.n && (!g.lower || gi0 >= gj)) {
+        f4 o;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[v] = cv[mi][ni][v] + g.alpha * (acc[mi][ni][v] * unscale);
+        *reinterpret_cast<f4*>(C + gi0 + (size_t)gj * g.ldc) = o;
+        continue;
+      }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int gi = row0 + wr + mi * 16 + 4 * (lane / 16) + v;
-        int gj = col0 + wc + ni * 16 + (lane & 15);
+        const int gi = gi0 + v;
         if (gi < g.m && gj < g.n && (!g.lower || gi >= gj)) {
           float* p = C + gi + (size_t)gj * g.ldc;
           *p = *p + g.alpha * (acc[mi][ni][v] * unscale);
         }
       }
+    }
 }
 
 }  // namespace

@@ -13,8 +13,13 @@ namespace cds {
 // kernel applies alpha to A (exact for the alpha = -1 of every caller).
 // transB = 1: op(B) = B^T with B stored n x k (ldb).
 // lower = 1: only C(i, j) with i >= j is computed and written (m == n).
-// For the FP16 operand mode, scale_exp[b] (device, may be null) is the power of
-// two applied to op(B) before rounding; the product is scaled back.
+// For the FP16 operand mode, op(B) is multiplied before rounding by the power of
+// two 2^e that brings max|op(B)| to [2^13, 2^14) (|e| <= 100), and the product by
+// 2^-e; max|op(B)| comes as kScaleParts partial maxima per matrix (scale_part,
+// written by launch_maxabs_part; one wave reduces them, so there are 64).  With
+// scaleA the A operand is multiplied by 2^e too (|e| <= 50) and the product by 2^-2e.
+constexpr int kScaleParts = 64;
+
 template <typename T>
 struct GemmArgs {
   int m, n, k;
@@ -24,7 +29,8 @@ struct GemmArgs {
   T alpha;
   int transB;
   int lower;
-  const int* scale_exp;
+  const float* scale_part;   // mode 2: kScaleParts partial maxima of |op(B)| per matrix, or null (no scaling)
+  int scaleA;                // mode 2: A takes the same power of two as op(B) (the two are one block, as in SYRK)
   const int32_t* guard;   // optional: the launch does nothing when *guard != 0
 };
 // mode: 0 native MFMA of T, 1 bf16 operands (T = float), 2 fp16 operands (T = float)

@@ -733,7 +733,7 @@ size_t getrf_ws_bytes(int n, int nb, int leaf, int batch, size_t elem) {
 
 template <typename T>
 cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, int32_t* ipiv, int64_t strideP,
-                            int32_t* info, int batch, int nb, int mode, int* scale_exp) {
+                            int32_t* info, int batch, int nb, int mode, float* scale_part) {
   if (batch <= 0) return CDS_SUCCESS;
   if (n == 0) {
     if (launch_fill_i32(info, batch, 0, c.s0) != hipSuccess) return CDS_HIP_ERROR;
@@ -828,12 +828,12 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
       }
       if (e != hipSuccess) return e;
       const int mrem = n - k - jb;
-      const int* sc = nullptr;
-      if (mrem > 0 && mode == 2 && scale_exp != nullptr) {
-        // power-of-two scale of this launch's U12 block (one slot per stream)
-        int* slot = scale_exp + (s == c.s0 ? 0 : batch);
+      const float* sc = nullptr;
+      if (mrem > 0 && mode == 2 && scale_part != nullptr) {
+        // partial maxima of this launch's U12 block for its power-of-two scale (one region per stream)
+        float* slot = scale_part + (s == c.s0 ? 0 : (size_t)batch * kScaleParts);
         if constexpr (std::is_same<T, float>::value) {
-          e = launch_maxabs_exp(A + k + (size_t)cb * lda, lda, strideA, jb, nc, slot, batch, s);
+          e = launch_maxabs_part(A + k + (size_t)cb * lda, lda, strideA, jb, nc, slot, batch, s);
           if (e != hipSuccess) return e;
         }
         sc = slot;
@@ -844,7 +844,7 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
         ga.A = A + (k + jb) + (size_t)k * lda; ga.lda = lda; ga.strideA = strideA;
         ga.B = A + k + (size_t)cb * lda; ga.ldb = lda; ga.strideB = strideA;
         ga.C = A + (k + jb) + (size_t)cb * lda; ga.ldc = lda; ga.strideC = strideA;
-        ga.alpha = (T)-1; ga.transB = 0; ga.lower = 0; ga.scale_exp = sc; ga.guard = nullptr;
+        ga.alpha = (T)-1; ga.transB = 0; ga.lower = 0; ga.scale_part = sc; ga.scaleA = 0; ga.guard = nullptr;
         KScope ks(c.timer, CDS_KC_UPDATE, s, batch * 2.0 * mrem * (double)nc * jb,
                   batch * (double)sizeof(T) * (2.0 * mrem * nc + (double)mrem * jb + (double)jb * nc));
         e = launch_gemm<T>(ga, batch, mode, s);
@@ -904,8 +904,8 @@ cds_status_t getrf_run(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, int32_
 template cds_status_t getrf_run<double>(Ctx&, int, double*, int64_t, int64_t, int32_t*, int64_t, int32_t*, int, int);
 template cds_status_t getrf_run<float>(Ctx&, int, float*, int64_t, int64_t, int32_t*, int64_t, int32_t*, int, int);
 template cds_status_t getrf_run_mode<float>(Ctx&, int, float*, int64_t, int64_t, int32_t*, int64_t, int32_t*, int,
-                                            int, int, int*);
+                                            int, int, float*);
 template cds_status_t getrf_run_mode<double>(Ctx&, int, double*, int64_t, int64_t, int32_t*, int64_t, int32_t*, int,
-                                             int, int, int*);
+                                             int, int, float*);
 
 }  // namespace cds

@@ -301,33 +301,24 @@ __global__ void copy_d_kernel(const double* A0, int64_t lda, int64_t strideA, do
   }
 }
 
-// power-of-two scale for FP16 update operands: 2^e * max|B| lands near 2^14
-__global__ void maxabs_exp_kernel(const float* B0, int64_t ldb, int64_t strideB, int rows, int cols, int* out,
-                                  int clear_only) {
-  (void)clear_only;
+// Partial maxima of |B| for the FP16 operand scale (the update kernel reduces the kScaleParts
+// values and derives the power of two).  Block p takes columns 4p + wave, 4p + wave + 4P, ...
+// (one wave per column, lanes down the rows).  NaN entries are ignored, as fmaxf does.
+__global__ void __launch_bounds__(256) maxabs_part_kernel(const float* B0, int64_t ldb, int64_t strideB, int rows,
+                                                          int cols, float* part) {
   const int b = blockIdx.y;
   const float* B = B0 + (size_t)b * strideB;
-  __shared__ float part[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ float red[4];
   float m = 0.f;
-  const int64_t total = (int64_t)rows * cols;
-  for (int64_t idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    const int i = (int)(idx % rows), j = (int)(idx / rows);
-    m = fmaxf(m, fabsf(B[i + (size_t)j * ldb]));
+  for (int j = blockIdx.x * 4 + wave; j < cols; j += kScaleParts * 4) {
+    const float* col = B + (size_t)j * ldb;
+    for (int i = lane; i < rows; i += 64) m = fmaxf(m, fabsf(col[i]));
   }
   m = wave_max(m);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+  if (lane == 0) red[wave] = m;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    float t = fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]));
-    int e = 0;
-    if (t > 0.f && t == t && t < INFINITY) {
-      int ex;
-      frexpf(t, &ex);      // t in [2^(ex-1), 2^ex)
-      e = 14 - ex;
-      e = max(-100, min(100, e));
-    }
-    out[b] = e;
-  }
+  if (threadIdx.x == 0) part[(size_t)b * kScaleParts + blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
 }
 
 // max_j sum_i |A(i, j)| = ||A^T||_inf; one wave per column
@@ -529,10 +520,12 @@ __global__ void fallback_result_kernel(int nrhs, const double* anorm, double* rn
 
 }  // namespace
 
-hipError_t launch_maxabs_exp(const float* B, int64_t ldb, int64_t strideB, int rows, int cols, int* out, int batch,
-                             hipStream_t s) {
-  if (rows <= 0 || cols <= 0) return hipSuccess;
-  hipLaunchKernelGGL(maxabs_exp_kernel, dim3(1, batch), dim3(256), 0, s, B, ldb, strideB, rows, cols, out, 0);
+hipError_t launch_maxabs_part(const float* B, int64_t ldb, int64_t strideB, int rows, int cols, float* part, int batch,
+                              hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  // an empty block still writes its kScaleParts zeros (no scaling)
+  hipLaunchKernelGGL(maxabs_part_kernel, dim3(kScaleParts, batch), dim3(256), 0, s, B, ldb, strideB, std::max(rows, 0),
+                     std::max(cols, 0), part);
   return hipGetLastError();
 }
 
@@ -548,16 +541,21 @@ hipError_t launch_outer(int m, int n, int k, double alpha, const double* X, int6
 
 // ---------------------------------------------------------------------------------
 // workspace of the refinement loop (after the error region):
-//   anorm, rnorm, xnorm, state, active, scale (2 per matrix), info, perm, gmap, R,
+//   anorm, rnorm, xnorm, state, active, scale partials (2 x kScaleParts per matrix), info, perm, gmap, R,
 //   [FP64 fallback copy and pivots], then the inner region for the factorization /
 //   solves (which keeps its own error region view at the same error word).
 // ---------------------------------------------------------------------------------
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 constexpr int kResChunks = 16;   // column chunks of the split residual
 
+// the block-inverse data of the FP32 factors (one right-hand side, LU only)
+static size_t binv_region(int n, int nrhs, int batch, int chol) {
+  return (!chol && nrhs == 1) ? al256((size_t)batch * binv_elems(n) * 4) : 0;
+}
+
 static size_t ir_small_bytes(int n, int nrhs, int batch) {
   return al256(batch * 8) + 2 * al256((size_t)batch * nrhs * 8) + al256(batch * sizeof(IrState)) +
-         al256(batch * 4) + al256(batch * 4 * 2) + al256(batch * 4) + 2 * al256((size_t)batch * n * 4) +
+         al256(batch * 4) + al256((size_t)batch * 4 * 2 * kScaleParts) + al256(batch * 4) + 2 * al256((size_t)batch * n * 4) +
          al256((size_t)batch * n * nrhs * 8) + al256((size_t)batch * kResChunks * n * 8);
 }
 
@@ -570,17 +568,18 @@ size_t ir_ws_bytes(int n, int nrhs, int batch, int nb, int chol, int fallback) {
     inner = std::max(inner, getrs_ws_bytes(n, nrhs, batch, 8));
     fb = al256((size_t)batch * n * n * 8) + al256((size_t)batch * n * 4) + al256(batch * 4);
   }
-  return kErrRegion + ir_small_bytes(n, nrhs, batch) + fb + inner;
+  return kErrRegion + ir_small_bytes(n, nrhs, batch) + binv_region(n, nrhs, batch, chol) + fb + inner;
 }
 
 struct IrWs {
-  double* anorm; double* rnorm; double* xnorm; IrState* st; int* active; int* scale; int32_t* info;
+  double* anorm; double* rnorm; double* xnorm; IrState* st; int* active; float* scale; int32_t* info;
   int32_t* perm; int32_t* gmap; double* R; double* part;
+  float* binv;   // block-inverse data of the factors, or null
   double* fbA; int32_t* fbpiv; int32_t* fbinfo;
   void* inner; size_t inner_bytes;
 };
 
-static bool carve(void* ws, size_t ws_bytes, int n, int nrhs, int batch, int fallback, IrWs& w) {
+static bool carve(void* ws, size_t ws_bytes, int n, int nrhs, int batch, int fallback, IrWs& w, int binv = 0) {
   w = IrWs{};
   char* p = (char*)ws + kErrRegion;
   w.anorm = (double*)p; p += al256(batch * 8);
@@ -588,12 +587,16 @@ static bool carve(void* ws, size_t ws_bytes, int n, int nrhs, int batch, int fal
   w.xnorm = (double*)p; p += al256((size_t)batch * nrhs * 8);
   w.st = (IrState*)p; p += al256(batch * sizeof(IrState));
   w.active = (int*)p; p += al256(batch * 4);
-  w.scale = (int*)p; p += al256(batch * 4 * 2);
+  w.scale = (float*)p; p += al256((size_t)batch * 4 * 2 * kScaleParts);
   w.info = (int32_t*)p; p += al256(batch * 4);
   w.perm = (int32_t*)p; p += al256((size_t)batch * n * 4);
   w.gmap = (int32_t*)p; p += al256((size_t)batch * n * 4);
   w.R = (double*)p; p += al256((size_t)batch * n * nrhs * 8);
   w.part = (double*)p; p += al256((size_t)batch * kResChunks * n * 8);
+  if (binv) {
+    w.binv = (float*)p;
+    p += binv_region(n, nrhs, batch, 0);
+  }
   if (fallback) {
     w.fbA = (double*)p; p += al256((size_t)batch * n * n * 8);
     w.fbpiv = (int32_t*)p; p += al256((size_t)batch * n * 4);
@@ -640,6 +643,7 @@ static cds_status_t refine(Ctx& c, const IrWs& w, int trans, int chol, int n, in
   g.B = B; g.ldb = ldb; g.strideB = strideB;
   g.X = X; g.ldx = ldx; g.strideX = strideX; g.accumulate = 0;
   g.active = nullptr; g.ws = w.inner; g.ws_bytes = w.inner_bytes;
+  g.binv = (!trans && !chol && nrhs == 1) ? w.binv : nullptr;
   cds_status_t st = getrs_core<float, double>(c, g);
   if (st != CDS_SUCCESS) return st;
   if (launch_fill_zero(w.rnorm, (size_t)batch * nrhs * 8, s) != hipSuccess) return CDS_HIP_ERROR;
@@ -829,7 +833,7 @@ cds_status_t gesv_mixed_run(Ctx& c, int prec, int n, int nrhs, const double* A, 
   if (batch == 0 || n == 0 || nrhs == 0) return CDS_SUCCESS;
   hipStream_t s = c.s0;
   IrWs w;
-  if (!carve(c.ws, c.ws_bytes, n, nrhs, batch, prm.fallback, w)) return CDS_WORKSPACE_TOO_SMALL;
+  if (!carve(c.ws, c.ws_bytes, n, nrhs, batch, prm.fallback, w, nrhs == 1)) return CDS_WORKSPACE_TOO_SMALL;
   if (launch_fill_zero(w.anorm, batch * 8, s) != hipSuccess) return CDS_HIP_ERROR;
   hipLaunchKernelGGL(convert_kernel, dim3((n + 63) / 64, batch), dim3(256), 0, s, A, lda, strideA, LU, (int64_t)n,
                      strideLU, n, w.anorm);
@@ -839,6 +843,11 @@ cds_status_t gesv_mixed_run(Ctx& c, int prec, int n, int nrhs, const double* A, 
   cds_status_t st = getrf_run_mode<float>(ci, n, LU, n, strideLU, ipiv, strideP, w.info, batch, nb, prec, w.scale);
   if (st != CDS_SUCCESS) return st;
   if (launch_perm(ipiv, strideP, n, w.perm, n, w.gmap, batch, s) != hipSuccess) return CDS_HIP_ERROR;
+  if (w.binv) {
+    KScope kb(c.timer, CDS_KC_TRSV, s, 0.0, 0.0);
+    if (launch_binv_prep(LU, n, strideLU, n, w.binv, (int64_t)binv_elems(n), batch, s) != hipSuccess)
+      return CDS_HIP_ERROR;
+  }
   st = refine(ci, w, 0, 0, n, nrhs, A, lda, strideA, LU, n, strideLU, w.perm, n, B, ldb, strideB, X, ldx, strideX,
               prm, res, w.info, batch);
   if (st != CDS_SUCCESS) return st;

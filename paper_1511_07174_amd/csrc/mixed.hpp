@@ -6,9 +6,9 @@ namespace cds {
 
 template <typename T>
 cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, int32_t* ipiv, int64_t strideP,
-                            int32_t* info, int batch, int nb, int mode, int* scale_exp);
+                            int32_t* info, int batch, int nb, int mode, float* scale_part);
 template <typename T>
-cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int nb, int mode, int* scale_exp);
+cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int nb, int mode, float* scale_part);
 
 size_t ir_ws_bytes(int n, int nrhs, int batch, int nb, int chol, int fallback);
 
@@ -29,8 +29,9 @@ cds_status_t gesv_gmres_ir_run(Ctx& c, int prec, int n, const double* A, int64_t
                                float* LU, int32_t* ipiv, const cds_ir_params_t& prm, const cds_krylov_params_t& kp,
                                cds_ir_result_t* res, int nb);
 
-hipError_t launch_maxabs_exp(const float* B, int64_t ldb, int64_t strideB, int rows, int cols, int* out, int batch,
-                             hipStream_t s);
+// kScaleParts partial maxima of |B| (rows x cols, column-major) per matrix into part[b * kScaleParts + p]
+hipError_t launch_maxabs_part(const float* B, int64_t ldb, int64_t strideB, int rows, int cols, float* part, int batch,
+                              hipStream_t s);
 hipError_t launch_outer(int m, int n, int k, double alpha, const double* X, int64_t ldx, int64_t strideX,
                         const double* Y, int64_t ldy, int64_t strideY, double* C, int64_t ldc, int64_t strideC,
                         int batch, hipStream_t s);

@@ -408,6 +408,221 @@ __global__ void __launch_bounds__(TNT) trsv1_kernel(TrsvArgs<T> a) {
   }
 }
 
+// ------------------------------------------------------------------------------------
+// Block-inverse substitution for one FP32 right-hand side: the refinement's correction
+// solves L y = P r, U d = y with the FP32 LU factors (Sec. 2, steps of the iterative
+// refinement).  With 128-row diagonal blocks D_b and the block M_{b,p} of the most
+// recent dependency p (b - 1 for L, b + 1 for U), block b's part of the solution is
+//     x_b = D_b^{-1} (r_b - sum_{c != p} M_{b,c} x_c) - K_b x_p,   K_b = D_b^{-1} M_{b,p}.
+// D_b^{-1} and K_b are formed once per factorization (binv_prep_kernel).  Everything
+// but the K_b x_p product uses blocks solved at least two steps earlier, so the chain
+// from one block to the next is one wait and one 128 x 128 matrix-vector product,
+// where substitution needs the product and 64-128 dependent steps.  The block solve
+// through D_b^{-1} has forward error of order cond(D_b) u instead of substitution's
+// componentwise backward stability; the refinement absorbs that, and getrs / potrs keep
+// the substitution kernels.
+// ------------------------------------------------------------------------------------
+constexpr int BB = 128;
+
+// grid (nblk, 2, batch): block bk of triangle tri (0: L, unit lower; 1: U, upper) of matrix b.
+// Output: D^{-1} then K, each 128 x 128 with element (i, t) at t * 128 + i, zero outside the
+// block's rows and columns (K: outside the dependency's columns; not written without one).
+__global__ void __launch_bounds__(256) binv_prep_kernel(const float* M0, int64_t lda, int64_t strideA, int n, int nblk,
+                                                        float* out0, int64_t strideO) {
+  const int bk = blockIdx.x, tri = blockIdx.y, b = blockIdx.z;
+  const float* M = M0 + (size_t)b * strideA;
+  float* Dinv = out0 + (size_t)b * strideO + ((size_t)tri * nblk + bk) * 2 * BB * BB;
+  float* K = Dinv + BB * BB;
+  __shared__ float D[BB][BB + 1];
+  __shared__ float X[BB][BB + 1];
+  const int tid = threadIdx.x;
+  const int r0 = bk * BB, rb = min(BB, n - r0);
+  for (int e = tid; e < BB * BB; e += 256) {
+    const int i = e % BB, t = e / BB;
+    D[i][t] = (i < rb && t < rb) ? M[(r0 + i) + (size_t)(r0 + t) * lda] : 0.f;
+  }
+  __syncthreads();
+  // column j of D^{-1} by substitution on e_j (thread j); every lane runs the same loop bounds
+  if (tid < BB) {
+    const int j = tid;
+    if (tri == 0) {
+      for (int i = 0; i < BB; ++i) {
+        float s = (i == j) ? 1.f : 0.f;
+        for (int t = 0; t < i; ++t) s = fmaf(-D[i][t], X[t][j], s);
+        X[i][j] = (i < rb && j < rb) ? s : 0.f;
+      }
+    } else {
+      for (int i = BB - 1; i >= 0; --i) {
+        float s = (i == j) ? 1.f : 0.f;
+        for (int t = i + 1; t < BB; ++t) s = fmaf(-D[i][t], X[t][j], s);
+        X[i][j] = (i < rb && j < rb) ? s / D[i][i] : 0.f;
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < BB * BB; e += 256) Dinv[e] = X[e % BB][e / BB];
+  const int dep = tri == 0 ? bk - 1 : bk + 1;
+  if (dep < 0 || dep >= nblk) return;   // uniform over the workgroup
+  const int c0 = dep * BB, cw = min(BB, n - c0);
+  for (int e = tid; e < BB * BB; e += 256) {
+    const int u = e % BB, t = e / BB;
+    D[u][t] = (u < rb && t < cw) ? M[(r0 + u) + (size_t)(c0 + t) * lda] : 0.f;
+  }
+  __syncthreads();
+  // thread (i, h): K(i, t) = sum_u D^{-1}(i, u) M(u, t) for t in [64 h, 64 h + 64), u ascending
+  const int i = tid % BB, t0 = (tid / BB) * 64;
+  float acc[64];
+#pragma unroll
+  for (int t = 0; t < 64; ++t) acc[t] = 0.f;
+  for (int u = 0; u < BB; ++u) {
+    const float xi = X[i][u];
+#pragma unroll
+    for (int t = 0; t < 64; ++t) acc[t] = fmaf(xi, D[u][t0 + t], acc[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < 64; ++t) K[(size_t)(t0 + t) * BB + i] = acc[t];
+}
+
+struct BinvArgs {
+  const float* M; int64_t lda; int64_t strideA;
+  const float* P; int64_t strideP;          // binv_prep_kernel's output per matrix
+  float* Y; int64_t strideY;                // right-hand side in, solution out (n per matrix)
+  uint64_t* slots; int64_t slot_stride;     // flag+payload word per row
+  int* tickets;                             // one per matrix
+  int* err;
+  const int* active;
+  int n, nblk, upper;
+  uint32_t flag;
+};
+
+// Persistent, ticket-ordered like trsv1_kernel.  Wave q covers rows 64 (q & 1) + lane of the
+// block and columns 64 (q >> 1) .. + 63 of every 128 x 128 block it multiplies; the two column
+// halves meet in LDS.  D_b^{-1} and K_b are staged in LDS before any waiting.
+template <int DEPTH>
+__global__ void __launch_bounds__(TNT, 1) trsv1_binv_kernel(BinvArgs a) {
+  const int b = blockIdx.z;
+  if (a.active && a.active[b] == 0) return;
+  const float* M = a.M + (size_t)b * a.strideA;
+  float* Y = a.Y + (size_t)b * a.strideY;
+  uint64_t* slots = a.slots + (size_t)b * a.slot_stride;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int q = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index, kept in a scalar register
+  const int ch = q >> 1;                  // column half
+  const int row = (q & 1) * 64 + lane;    // row of the block
+  __shared__ int s_ticket;
+  __shared__ float sD[BB][BB];            // D^{-1}: element (i, t) at [t][i]
+  __shared__ float sK[BB][BB];            // K, the same layout
+  __shared__ float sv[BB];
+  __shared__ float red[2][BB];
+  __shared__ float red2[2][BB];
+  if (tid == 0) s_ticket = atomicAdd(a.tickets + b, 1);
+  __syncthreads();
+  const int lb = s_ticket;
+  if (lb >= a.nblk) return;
+  const int bk = a.upper ? (a.nblk - 1 - lb) : lb;
+  const int r0 = bk * BB, rb = min(BB, a.n - r0);
+  const bool rok = row < rb;
+  const int ndep = lb;
+  auto dep_block = [&](int d) { return a.upper ? (a.nblk - 1 - d) : d; };
+  const float* Pb = a.P + (size_t)b * a.strideP + ((size_t)a.upper * a.nblk + bk) * 2 * BB * BB;
+
+  // independent of every other block: D^{-1} and K to LDS, the right-hand side
+  for (int e = tid; e < BB * BB; e += TNT) (&sD[0][0])[e] = Pb[e];
+  if (ndep > 0)
+    for (int e = tid; e < BB * BB; e += TNT) (&sK[0][0])[e] = Pb[BB * BB + e];
+  const float rhs = (ch == 0 && rok) ? Y[r0 + row] : 0.f;
+
+  float mbuf[DEPTH][64];
+  // A wave-uniform base per block of columns and a 32-bit element offset per lane, advanced by
+  // lda per column (64 lda + 128 stays far below 2^32).  The offset is made opaque after every
+  // step so that the 64 offsets are formed one at a time instead of being kept live across the
+  // loop.  Rows past the end read the block's last row (their results are discarded); columns
+  // past the end are read only in the last, partial block of columns, under a mask.
+  const unsigned ldu = (unsigned)a.lda;
+  const unsigned rowc = (unsigned)(rok ? row : rb - 1);
+  auto load = [&](float* dst, int cb) {
+    const int c0 = cb * BB + ch * 64;
+    const float* base = M + r0 + (size_t)c0 * a.lda;
+    unsigned off = rowc;
+    if (c0 + 64 <= a.n) {
+#pragma unroll
+      for (int t = 0; t < 64; ++t) {
+        dst[t] = base[off];
+        off += ldu;
+        asm volatile("" : "+v"(off));
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 64; ++t) {
+        dst[t] = c0 + t < a.n ? base[off] : 0.f;
+        off += ldu;
+        asm volatile("" : "+v"(off));
+      }
+    }
+  };
+  const int nstream = ndep > 0 ? ndep - 1 : 0;   // dependencies before the most recent one
+#pragma unroll
+  for (int s = 0; s < DEPTH; ++s)
+    if (s < nstream) load(mbuf[s], dep_block(s));
+  float acc0 = 0.f, acc1 = 0.f;
+  for (int d0 = 0; d0 < nstream; d0 += DEPTH) {
+#pragma unroll
+    for (int s = 0; s < DEPTH; ++s) {
+      const int d = d0 + s;
+      if (d < nstream) {
+        const int idx = dep_block(d) * BB + ch * 64 + lane;
+        const uint64_t* p[1] = {slots + idx};
+        const bool v[1] = {idx < a.n};
+        float y[1];
+        ll_wait_vals<float, 1>(p, v, a.flag, a.err, y);
+#pragma unroll
+        for (int t = 0; t < 64; t += 2) {
+          acc0 = fmaf(mbuf[s][t], lane_bcast(y[0], t), acc0);
+          acc1 = fmaf(mbuf[s][t + 1], lane_bcast(y[0], t + 1), acc1);
+        }
+        if (d + DEPTH < nstream) load(mbuf[s], dep_block(d + DEPTH));
+      }
+    }
+  }
+  // v = r - (products so far), then c = D^{-1} v
+  red[ch][row] = acc0 + acc1;
+  __syncthreads();
+  if (ch == 0) sv[row] = rok ? rhs - (red[0][row] + red[1][row]) : 0.f;
+  __syncthreads();
+  float c0p = 0.f, c1p = 0.f;
+#pragma unroll 8
+  for (int t = 0; t < 64; t += 2) {
+    c0p = fmaf(sD[ch * 64 + t][row], sv[ch * 64 + t], c0p);
+    c1p = fmaf(sD[ch * 64 + t + 1][row], sv[ch * 64 + t + 1], c1p);
+  }
+  red[ch][row] = c0p + c1p;   // the reads of red above finished before the last barrier
+  __syncthreads();
+  float x = red[0][row] + red[1][row];
+  if (ndep > 0) {
+    // the chain step: x -= K x_p as soon as x_p is published
+    const int idx = dep_block(ndep - 1) * BB + ch * 64 + lane;
+    const uint64_t* p[1] = {slots + idx};
+    const bool v[1] = {idx < a.n};
+    float y[1];
+    ll_wait_vals<float, 1>(p, v, a.flag, a.err, y);
+    float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+#pragma unroll
+    for (int t = 0; t < 64; t += 4) {
+      p0 = fmaf(sK[ch * 64 + t][row], lane_bcast(y[0], t), p0);
+      p1 = fmaf(sK[ch * 64 + t + 1][row], lane_bcast(y[0], t + 1), p1);
+      p2 = fmaf(sK[ch * 64 + t + 2][row], lane_bcast(y[0], t + 2), p2);
+      p3 = fmaf(sK[ch * 64 + t + 3][row], lane_bcast(y[0], t + 3), p3);
+    }
+    red2[ch][row] = (p0 + p1) + (p2 + p3);
+    __syncthreads();
+    x -= red2[0][row] + red2[1][row];
+  }
+  if (ch == 0 && rok) {
+    ll_store_val(slots + (r0 + row), x, a.flag);
+    Y[r0 + row] = x;
+  }
+}
+
 template <typename T, int NR>
 hipError_t launch_trsv_nr(const TrsvArgs<T>& a, int batch, hipStream_t s) {
   dim3 grid(a.nblk, a.groups, batch);
@@ -424,7 +639,20 @@ size_t trsv_slot_bytes(int n, int nrhs, int batch, size_t elem) {
   const int groups = (nrhs + nr - 1) / nr;
   const int nblk = (n + BS - 1) / BS;
   const int llw = elem == 8 ? 2 : 1;
-  return (size_t)batch * groups * nblk * BS * nr * llw * 8;
+  // one right-hand side may also take the block-inverse kernel (128-row blocks)
+  const size_t rows = nr == 1 ? std::max<size_t>((size_t)nblk * BS, (size_t)((n + BB - 1) / BB) * BB)
+                              : (size_t)nblk * BS;
+  return (size_t)batch * groups * rows * nr * llw * 8;
+}
+
+size_t binv_elems(int n) { return (size_t)2 * ((n + BB - 1) / BB) * 2 * BB * BB; }
+
+hipError_t launch_binv_prep(const float* LU, int64_t lda, int64_t strideA, int n, float* out, int64_t strideO,
+                            int batch, hipStream_t s) {
+  if (n <= 0 || batch <= 0) return hipSuccess;
+  const int nblk = (n + BB - 1) / BB;
+  hipLaunchKernelGGL(binv_prep_kernel, dim3(nblk, 2, batch), dim3(256), 0, s, LU, lda, strideA, n, nblk, out, strideO);
+  return hipGetLastError();
 }
 
 size_t getrs_ws_bytes(int n, int nrhs, int batch, size_t elem) {
@@ -508,7 +736,23 @@ cds_status_t getrs_core(Ctx& c, const GetrsCore<T, S>& g) {
     hipError_t e;
     KScope ks(c.timer, CDS_KC_TRSV, s, (double)batch * n * (double)n * nrhs,
               (double)batch * sizeof(T) * ((double)n * n / 2.0 * groups + 2.0 * n * nrhs));
-    if (nr == 1) {
+    bool done = false;
+    if constexpr (std::is_same<T, float>::value) {
+      if (g.binv != nullptr && !g.trans && !g.chol && nrhs == 1) {
+        BinvArgs bv;
+        bv.M = g.M; bv.lda = g.lda; bv.strideA = g.strideA;
+        bv.P = g.binv; bv.strideP = (int64_t)binv_elems(n);
+        bv.Y = temp; bv.strideY = strideT;
+        bv.n = n; bv.nblk = (n + BB - 1) / BB; bv.upper = pass;
+        bv.slots = slots; bv.slot_stride = (int64_t)bv.nblk * BB;
+        bv.tickets = tickets; bv.err = c.err; bv.active = g.active; bv.flag = a.flag;
+        hipLaunchKernelGGL(trsv1_binv_kernel<2>, dim3(bv.nblk, 1, batch), dim3(TNT), 0, s, bv);
+        e = hipGetLastError();
+        done = true;
+      }
+    }
+    if (done) {
+    } else if (nr == 1) {
       hipLaunchKernelGGL((trsv1_kernel<T, 4>), dim3(a.nblk, 1, batch), dim3(TNT), 0, s, a);
       e = hipGetLastError();
     }

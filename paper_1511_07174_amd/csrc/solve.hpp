@@ -21,12 +21,20 @@ struct GetrsCore {
   int accumulate;
   const int* active;
   void* ws; size_t ws_bytes;
+  // optional (FP32 factors, op N, one right-hand side): launch_binv_prep's output for M, which
+  // switches the two triangular solves to the block-inverse kernel
+  const float* binv;
 };
 
 template <typename T, typename S>
 cds_status_t getrs_core(Ctx& c, const GetrsCore<T, S>& g);
 
 size_t trsv_slot_bytes(int n, int nrhs, int batch, size_t elem);
+// Diagonal-block inverses and chain products of the LU factors for the block-inverse solve:
+// binv_elems(n) floats per matrix, filled by launch_binv_prep from the factors of getrf.
+size_t binv_elems(int n);
+hipError_t launch_binv_prep(const float* LU, int64_t lda, int64_t strideA, int n, float* out, int64_t strideO,
+                            int batch, hipStream_t s);
 hipError_t launch_perm(const int32_t* ipiv, int64_t strideP, int n, int32_t* perm, int64_t strideQ, int32_t* gmap,
                        int batch, hipStream_t s);
 

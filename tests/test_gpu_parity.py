@@ -260,12 +260,67 @@ def test_gesv_mixed_uniform(cds):
     assert oracle.eta_inf(A, host(Xd), B[:, 0]) <= 1e-14
 
 
-def test_posv_mixed(cds):
+def test_block_inverse_first_solve(cds):
+    """The refinement solves one right-hand side with the FP32 factors through 128 x 128 diagonal-block
+    inverses.  With no refinement step (max_iter = 0) the result is that solve's x0, and its residual
+    against the same factors, ||P b - L U x0|| / (|| |L| |U| || ||x0||) (infinity norms), is held to
+    8 * 128 * u32 * max_b cond(D_b) over the diagonal blocks D_b of L and U: a block solved through an
+    explicit inverse leaves a residual of at most about 2 * 128 * u * cond(D_b) ||v||, for each of the two
+    triangles, with a factor 2 of margin.  n = 1000 spans seven full blocks and a ragged one."""
+    n = 1000
+    A, _, B = synth.uniform_system(n, 1, 31)
+    b = B[:, 0]
+    d = dev()
+    Ad = cds.colmajor(to_dev(A))
+    X = torch.zeros(n, dtype=torch.float64, device=d)
+    LU = torch.empty(n * n, dtype=torch.float32, device=d)
+    ipiv = torch.zeros(n, dtype=torch.int32, device=d)
+    res = torch.zeros(cds.cds.IR_RESULT_BYTES, dtype=torch.uint8, device=d)
+    cds.handle().gesv_mixed(Ad, to_dev(b), X, LU, ipiv, res, precision="fp32",
+                            params=cds.default_params(max_iter=0))
+    x0 = host(X)
+    F = host(LU).astype(np.float64).reshape(n, n).T     # column-major storage
+    L, U = oracle.unpack_lu(F)
+    perm = oracle.ipiv_to_perm(host(ipiv))
+    r = b[perm] - L @ (U @ x0)
+    eta = np.max(np.abs(r)) / (np.max(np.sum(np.abs(L) @ np.abs(U), axis=1)) * np.max(np.abs(x0)))
+    kmax = 0.0
+    for k in range(0, n, 128):
+        e = min(n, k + 128)
+        for T in (L[k:e, k:e], U[k:e, k:e]):
+            kmax = max(kmax, np.linalg.norm(T, np.inf) * np.linalg.norm(np.linalg.inv(T), np.inf))
+    assert eta <= 8 * 128 * 2.0 ** -24 * kmax, (eta, kmax)
+    no_device_error(cds)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_posv_mixed(cds, prec):
     n = 800
     A, X, B = synth.spd_system(n, 2, 6)
-    Xd, res = cds.solve(to_dev(A), to_dev(B), precision="fp32", spd=True)
+    Xd, res = cds.solve(to_dev(A), to_dev(B), precision=prec, spd=True)
     assert res[0].converged, res[0]
     assert oracle.eta_inf(A, host(Xd), B) <= 1e-14
+
+
+@pytest.mark.parametrize("spd", [False, True])
+def test_fp16_operand_scale_is_exact(cds, spd):
+    """The FP16 update multiplies op(B) by a power of two taken from max|op(B)| and the product by its
+    inverse.  Every scaling on the path is then exact, so the system times 2^-24 must give the bitwise
+    same solution and step count as the system itself (a scale taken from the wrong block, or not
+    undone, breaks this; without the scale 2^-24 U12 would fall below FP16's normal range)."""
+    n = 1200
+    if spd:
+        A, _, B = synth.spd_system(n, 1, 21)
+        b = B[:, 0]
+    else:
+        A, _, b, _ = synth.householder_system(n, 1e2, seed=21)
+    s = 2.0 ** -24
+    x1, r1 = cds.solve(to_dev(A), to_dev(b), precision="fp16", spd=spd)
+    x2, r2 = cds.solve(to_dev(A * s), to_dev(b * s), precision="fp16", spd=spd)
+    assert r1[0].converged and r2[0].converged, (r1[0], r2[0])
+    assert r1[0].iters == r2[0].iters
+    assert np.array_equal(host(x1), host(x2))
+    no_device_error(cds)
 
 
 # ------------------------------------------------------------------------ differentiable solve

@@ -65,8 +65,8 @@ def test_noalloc_rejects_what_the_scratch_cannot_hold(cds):
     t = torch.zeros(64, dtype=torch.float64, device=d)
     p = ctypes.c_void_p(t.data_ptr())
     prm = cds.default_params()
-    # n = 65536 with 32 right-hand sides needs about 50 MiB of scratch: refused before any work
-    assert L.cds_dgesv_mixed_noalloc(h.h, 0, 65536, 32, p, 65536, p, 65536, p, 65536, p, p, ctypes.byref(prm), p) == 5
+    # n = 65536 with one right-hand side needs about 138 MiB of scratch: refused before any work
+    assert L.cds_dgesv_mixed_noalloc(h.h, 0, 65536, 1, p, 65536, p, 65536, p, 65536, p, p, ctypes.byref(prm), p) == 5
     fb = cds.default_params(fallback=1)
     assert L.cds_dgesv_mixed_noalloc(h.h, 0, 8, 1, p, 8, p, 8, p, 8, p, p, ctypes.byref(fb), p) == 6
     assert L.cds_dgesv_mixed_noalloc(h.h, 0, 8, 1, p, 7, p, 8, p, 8, p, p, ctypes.byref(prm), p) == 1
