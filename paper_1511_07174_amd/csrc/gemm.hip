@@ -7,6 +7,9 @@
 //
 // Design: 256-thread workgroups (4 waves, 2 x 2), a 128 x 128 C tile per
 // workgroup, 64 x 64 per wave = 4 x 4 MFMA 16x16 blocks held in accumulators.
+// Launches with fewer than two 128-tiles per compute unit (the look-ahead's
+// next-panel columns, the last trailing matrices) take 64 x 64 tiles, so that
+// four times as many workgroups share the k-loop.
 // A and B tiles are staged through LDS, double-buffered with a register
 // prefetch of the next K-slice.  FP64 uses v_mfma_f64_16x16x4, FP32
 // v_mfma_f32_16x16x4; the mixed variants read FP32 data, round it to BF16 or
@@ -69,11 +72,13 @@ __device__ __forceinline__ T ldg_or_zero(const T* p, bool ok) { return ok ? *p :
 // VEC: 16-byte global loads (host checked the alignment of A, B and the leading
 // dimensions); edge vectors fall back to element loads with bounds checks.
 // ------------------------------------------------------------------------------------
-template <typename T, bool VEC>
+template <typename T, bool VEC, int TB>
 __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && VEC) ? 3 : 2)
 gemm_native_kernel(GemmArgs<T> g) {
   if (g.guard && *g.guard != 0) return;
   constexpr int BK = GemmCfg<T, 0>::BK;
+  constexpr int BM = TB, BN = TB;   // C tile
+  constexpr int MB = TB / 32;       // 16 x 16 blocks per wave and dimension (2 x 2 waves)
   constexpr int PADM = BM + 4;  // row pitch in LDS (elements); PADM * sizeof(T) is a multiple of 16
   constexpr int NV = VEC ? 16 / (int)sizeof(T) : 1;   // elements per global load
   __shared__ __attribute__((aligned(16))) T As[2][BK][PADM];
@@ -92,7 +97,7 @@ gemm_native_kernel(GemmArgs<T> g) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = (wave & 1) * 64, wc = (wave >> 1) * 64;
+  const int wr = (wave & 1) * (TB / 2), wc = (wave >> 1) * (TB / 2);
 
   constexpr int A_PER = BM * BK / NT / NV;  // vectors per thread per tile
   constexpr int B_PER = BK * BN / NT / NV;
@@ -213,11 +218,11 @@ gemm_native_kernel(GemmArgs<T> g) {
       gj = col0 + wc + ni * 16 + (lane & 15);
     }
   };
-  acc_t acc[4][4];
+  acc_t acc[MB][MB];
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+  for (int mi = 0; mi < MB; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 4; ++ni) {
+    for (int ni = 0; ni < MB; ++ni) {
       int gi0, gj0;
       if (c_group(mi, ni, gi0, gj0)) {
         if constexpr (CV4) acc[mi][ni] = *reinterpret_cast<const f4*>(C + gi0 + (size_t)gj0 * g.ldc);
@@ -239,24 +244,24 @@ gemm_native_kernel(GemmArgs<T> g) {
     const int buf = kt & 1;
     if (kt + 1 < ktiles) load_tile((kt + 1) * BK);
     // fragments of k-step s + 1 are read from LDS while the MFMAs of step s run
-    T af[2][4], bf[2][4];
+    T af[2][MB], bf[2][MB];
 #pragma unroll
-    for (int mi = 0; mi < 4; ++mi) af[0][mi] = As[buf][lane / 16][wr + mi * 16 + (lane & 15)];
+    for (int mi = 0; mi < MB; ++mi) af[0][mi] = As[buf][lane / 16][wr + mi * 16 + (lane & 15)];
 #pragma unroll
-    for (int ni = 0; ni < 4; ++ni) bf[0][ni] = Bs[buf][lane / 16][wc + ni * 16 + (lane & 15)];
+    for (int ni = 0; ni < MB; ++ni) bf[0][ni] = Bs[buf][lane / 16][wc + ni * 16 + (lane & 15)];
 #pragma unroll
     for (int s = 0; s < BK / 4; ++s) {
       const int cur = s & 1, nxt = cur ^ 1;
       if (s + 1 < BK / 4) {
 #pragma unroll
-        for (int mi = 0; mi < 4; ++mi) af[nxt][mi] = As[buf][(s + 1) * 4 + lane / 16][wr + mi * 16 + (lane & 15)];
+        for (int mi = 0; mi < MB; ++mi) af[nxt][mi] = As[buf][(s + 1) * 4 + lane / 16][wr + mi * 16 + (lane & 15)];
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni) bf[nxt][ni] = Bs[buf][(s + 1) * 4 + lane / 16][wc + ni * 16 + (lane & 15)];
+        for (int ni = 0; ni < MB; ++ni) bf[nxt][ni] = Bs[buf][(s + 1) * 4 + lane / 16][wc + ni * 16 + (lane & 15)];
       }
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi)
+      for (int mi = 0; mi < MB; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni) {
+        for (int ni = 0; ni < MB; ++ni) {
           // FP64 forms the transposed block (operands swapped): lane & 15 then runs down the rows of C
           if constexpr (std::is_same<T, double>::value)
             acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[cur][ni], af[cur][mi], acc[mi][ni], 0, 0, 0);
@@ -264,12 +269,12 @@ gemm_native_kernel(GemmArgs<T> g) {
             acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[cur][mi], bf[cur][ni], acc[mi][ni], 0, 0, 0);
         }
 #if CDS_GEMM_SCHED
-      // spread the next step's 8 fragment reads between this step's 16 MFMAs
+      // spread the next step's 2 MB fragment reads between this step's MB^2 MFMAs
       if (s + 1 < BK / 4) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // 2 MFMA
-          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // 1 LDS read
+        for (int q = 0; q < 2 * MB; ++q) {
+          __builtin_amdgcn_sched_group_barrier(0x008, MB / 2, 0);   // MB / 2 MFMA
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);        // 1 LDS read
         }
       }
 #endif
@@ -280,9 +285,9 @@ gemm_native_kernel(GemmArgs<T> g) {
 
   // epilogue: store only
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+  for (int mi = 0; mi < MB; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 4; ++ni) {
+    for (int ni = 0; ni < MB; ++ni) {
       int gi0, gj0;
       if (c_group(mi, ni, gi0, gj0)) {
         if constexpr (CV4) *reinterpret_cast<f4*>(C + gi0 + (size_t)gj0 * g.ldc) = acc[mi][ni];
@@ -481,10 +486,18 @@ hipError_t launch_gemm(const GemmArgs<T>& g, int batch, int mode, hipStream_t s)
   const bool vec = ((uintptr_t)g.A % 16 == 0) && ((uintptr_t)g.B % 16 == 0) && (g.lda % nv == 0) &&
                    (g.ldb % nv == 0) && (g.strideA % nv == 0) && (g.strideB % nv == 0);
   if (mode == 0) {
-    if (vec)
-      hipLaunchKernelGGL((gemm_native_kernel<T, true>), grid, dim3(NT), 0, s, g);
-    else
-      hipLaunchKernelGGL((gemm_native_kernel<T, false>), grid, dim3(NT), 0, s, g);
+    if (tiles < 2 * 256) {
+      const int tm64 = (g.m + 63) / 64, tn64 = (g.n + 63) / 64;
+      const dim3 grid64(g.lower ? tm64 * (tm64 + 1) / 2 : tm64 * tn64, batch);
+      if (vec)
+        hipLaunchKernelGGL((gemm_native_kernel<T, true, 64>), grid64, dim3(NT), 0, s, g);
+      else
+        hipLaunchKernelGGL((gemm_native_kernel<T, false, 64>), grid64, dim3(NT), 0, s, g);
+    } else if (vec) {
+      hipLaunchKernelGGL((gemm_native_kernel<T, true, 128>), grid, dim3(NT), 0, s, g);
+    } else {
+      hipLaunchKernelGGL((gemm_native_kernel<T, false, 128>), grid, dim3(NT), 0, s, g);
+    }
   } else {
     if constexpr (std::is_same<T, float>::value) {
       if (mode == 1)
