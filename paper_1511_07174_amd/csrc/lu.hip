@@ -668,26 +668,28 @@ __global__ void __launch_bounds__(PNT, 2) panel_kernel(PanelArgs<T> P) {
 }
 
 // Apply the panel's interchanges (per-leaf move lists) to column ranges
-// [c_lo1, c_hi1) and [c_lo2, c_hi2).  One wave per column at a time.
+// [c_lo1, c_hi1) and [c_lo2, c_hi2), and (rowid non-null) to the int32 row-order
+// vector rowid, which then follows the rows as one more column.  One wave per
+// column at a time.
 template <typename T, int W>
 __global__ void __launch_bounds__(256) laswp_kernel(T* A0, int64_t lda, int64_t strideA, const int2* pairs0,
                                                     const int* cnt0, int64_t pairs_stride, int cnt_stride,
-                                                    int nleaves, int c_lo1, int c_hi1, int c_lo2, int c_hi2) {
+                                                    int nleaves, int c_lo1, int c_hi1, int c_lo2, int c_hi2,
+                                                    int32_t* rowid0, int64_t strideR) {
   const int b = blockIdx.y;
   T* A = A0 + (size_t)b * strideA;
   const int2* pairs = pairs0 + (size_t)b * pairs_stride;
   const int* cnt = cnt0 + (size_t)b * cnt_stride;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int n1 = c_hi1 - c_lo1, n2 = c_hi2 - c_lo2, ncols = n1 + n2;
+  const int n1 = c_hi1 - c_lo1, n2 = c_hi2 - c_lo2, ncols = n1 + n2 + (rowid0 != nullptr ? 1 : 0);
   constexpr int MAXE = 3 * W;
   constexpr int PER = (MAXE + 63) / 64;
-  for (int cidx = blockIdx.x * 4 + wave; cidx < ncols; cidx += gridDim.x * 4) {
-    const int col = cidx < n1 ? c_lo1 + cidx : c_lo2 + (cidx - n1);
-    T* colp = A + (size_t)col * lda;
+  auto move = [&](auto* colp) {
+    typedef typename std::remove_pointer<decltype(colp)>::type E;
     for (int l = 0; l < nleaves; ++l) {
       const int ne = cnt[l];
       const int2* pl = pairs + l * MAXE;
-      T v[PER];
+      E v[PER];
       int dst[PER];
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
@@ -702,7 +704,20 @@ __global__ void __launch_bounds__(256) laswp_kernel(T* A0, int64_t lda, int64_t 
       for (int q = 0; q < PER; ++q)
         if (dst[q] >= 0) colp[dst[q]] = v[q];
     }
+  };
+  for (int cidx = blockIdx.x * 4 + wave; cidx < ncols; cidx += gridDim.x * 4) {
+    if (cidx == n1 + n2) {
+      move(rowid0 + (size_t)b * strideR);
+    } else {
+      const int col = cidx < n1 ? c_lo1 + cidx : c_lo2 + (cidx - n1);
+      move(A + (size_t)col * lda);
+    }
   }
+}
+
+__global__ void iota_kernel(int32_t* p0, int64_t stride, int n) {
+  int32_t* p = p0 + (size_t)blockIdx.y * stride;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = i;
 }
 
 constexpr int kLeaf = 32;
@@ -733,7 +748,7 @@ size_t getrf_ws_bytes(int n, int nb, int leaf, int batch, size_t elem) {
 
 template <typename T>
 cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, int32_t* ipiv, int64_t strideP,
-                            int32_t* info, int batch, int nb, int mode, float* scale_part) {
+                            int32_t* info, int batch, int nb, int mode, float* scale_part, int32_t* perm_out) {
   if (batch <= 0) return CDS_SUCCESS;
   if (n == 0) {
     if (launch_fill_i32(info, batch, 0, c.s0) != hipSuccess) return CDS_HIP_ERROR;
@@ -766,6 +781,12 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
   hipStream_t s0 = c.s0, s1 = c.s1;
   if (launch_fill_i32(info, batch, 0, s0) != hipSuccess) return CDS_HIP_ERROR;
   if (launch_fill_zero(slots, (size_t)slot_words * 8 * batch, s0) != hipSuccess) return CDS_HIP_ERROR;
+  if (perm_out != nullptr) {
+    // the row order starts as the identity and follows every interchange (n per matrix)
+    hipLaunchKernelGGL(iota_kernel, dim3(std::min(1024, (n + 255) / 256), batch), dim3(256), 0, s0, perm_out,
+                       (int64_t)n, n);
+    if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
+  }
 
   const bool la = c.lookahead && n > nb && batch == 1;
   // s1 joins s0's work so far
@@ -809,11 +830,13 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
     const int* pc = cnts + (size_t)parity * batch * nleaves;
     int lo1 = 0, hi1 = left ? k : 0;
     int ncols = (hi1 - lo1) + (ce - cb);
-    if (ncols > 0) {
-      int blocks = std::min(4096, (ncols + 3) / 4);
+    // the row order follows each panel's interchanges once, with the left columns
+    int32_t* rid = left ? perm_out : nullptr;
+    if (ncols > 0 || rid != nullptr) {
+      int blocks = std::min(4096, (ncols + (rid ? 1 : 0) + 3) / 4);
       KScope ks(c.timer, CDS_KC_LASWP, s, 0.0, batch * 4.0 * sizeof(T) * jb * (double)ncols);
       hipLaunchKernelGGL((laswp_kernel<T, kLeaf>), dim3(blocks, batch), dim3(256), 0, s, A, lda, strideA, pr, pc,
-                         pairs_stride, nleaves, nl, lo1, hi1, cb, ce);
+                         pairs_stride, nleaves, nl, lo1, hi1, cb, ce, rid, (int64_t)n);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
@@ -898,14 +921,14 @@ cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, i
 template <typename T>
 cds_status_t getrf_run(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, int32_t* ipiv, int64_t strideP,
                        int32_t* info, int batch, int nb) {
-  return getrf_run_mode<T>(c, n, A, lda, strideA, ipiv, strideP, info, batch, nb, 0, nullptr);
+  return getrf_run_mode<T>(c, n, A, lda, strideA, ipiv, strideP, info, batch, nb, 0, nullptr, nullptr);
 }
 
 template cds_status_t getrf_run<double>(Ctx&, int, double*, int64_t, int64_t, int32_t*, int64_t, int32_t*, int, int);
 template cds_status_t getrf_run<float>(Ctx&, int, float*, int64_t, int64_t, int32_t*, int64_t, int32_t*, int, int);
 template cds_status_t getrf_run_mode<float>(Ctx&, int, float*, int64_t, int64_t, int32_t*, int64_t, int32_t*, int,
-                                            int, int, float*);
+                                            int, int, float*, int32_t*);
 template cds_status_t getrf_run_mode<double>(Ctx&, int, double*, int64_t, int64_t, int32_t*, int64_t, int32_t*, int,
-                                             int, int, float*);
+                                             int, int, float*, int32_t*);
 
 }  // namespace cds

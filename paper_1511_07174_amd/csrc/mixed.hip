@@ -26,9 +26,12 @@ __device__ __forceinline__ void atomic_max_nonneg(double* p, double v) {
   atomicMax(reinterpret_cast<unsigned long long*>(p), bits);
 }
 
-// One workgroup per 64 rows; wave w streams the columns j = w, w+4, ...
+// One workgroup per 64 rows; wave w streams the columns j = w, w+4, ...  Columns [jlo, jhi) are
+// converted; with anorm the row sums run over every column (in the same order whatever jlo and
+// jhi), otherwise only [jlo, jhi) is read.
 __global__ void __launch_bounds__(256) convert_kernel(const double* A0, int64_t lda, int64_t strideA, float* B0,
-                                                      int64_t ldb, int64_t strideB, int n, double* anorm) {
+                                                      int64_t ldb, int64_t strideB, int n, double* anorm, int jlo,
+                                                      int jhi) {
   const int b = blockIdx.y;
   const double* A = A0 + (size_t)b * strideA;
   float* Bf = B0 + (size_t)b * strideB;
@@ -36,20 +39,23 @@ __global__ void __launch_bounds__(256) convert_kernel(const double* A0, int64_t 
   const int r = blockIdx.x * 64 + lane;
   __shared__ double part[4][64];
   double s = 0.0;
+  const int j0s = anorm ? 0 : jlo, j1s = anorm ? n : jhi;
   if (r < n) {
     // 8 columns per step and wave (32 per workgroup step): 8 loads in flight per lane
-    for (int j0 = wave; j0 < n; j0 += 32) {
+    for (int j0 = j0s + wave; j0 < j1s; j0 += 32) {
       double v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = j0 + 4 * u < n ? A[r + (size_t)(j0 + 4 * u) * lda] : 0.0;
+      for (int u = 0; u < 8; ++u) v[u] = j0 + 4 * u < j1s ? A[r + (size_t)(j0 + 4 * u) * lda] : 0.0;
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (j0 + 4 * u < n) {
-          Bf[r + (size_t)(j0 + 4 * u) * ldb] = (float)v[u];
+        if (j0 + 4 * u < j1s) {
+          const int j = j0 + 4 * u;
+          if (j >= jlo && j < jhi) Bf[r + (size_t)j * ldb] = (float)v[u];
           s += fabs(v[u]);
         }
     }
   }
+  if (anorm == nullptr) return;   // uniform over the workgroup
   part[wave][lane] = s;
   __syncthreads();
   if (wave == 0) {
@@ -694,16 +700,6 @@ static cds_status_t refine(Ctx& c, const IrWs& w, int trans, int chol, int n, in
                        prm.success_tol, (const double*)w.anorm, w.rnorm, w.xnorm, w.st, res, w.active, info);
     if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
     if (it == max_iter) break;
-    if (prm.host_check) {
-      // read the active flags on the host (synchronises the stream) and leave early
-      h_active.resize(batch);
-      if (hipMemcpyAsync(h_active.data(), w.active, sizeof(int) * batch, hipMemcpyDeviceToHost, s) != hipSuccess)
-        return CDS_HIP_ERROR;
-      if (hipStreamSynchronize(s) != hipSuccess) return CDS_HIP_ERROR;
-      bool any = false;
-      for (int v : h_active) any = any || v;
-      if (!any) break;
-    }
     if (gm) {
       // the host decides whether another correction is needed (the GMRES solve is host-driven)
       int act = 0;
@@ -722,12 +718,27 @@ static cds_status_t refine(Ctx& c, const IrWs& w, int trans, int chol, int n, in
       if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
       continue;
     }
+    // With host_check the host reads the stop flags of this step and leaves early.  The flags are
+    // copied on the second stream after this step's control kernel, while the correction solve is
+    // already queued on the first: the device runs the solve while the host waits, and a solve
+    // queued after the last step finds no active system and returns at once.
+    if (prm.host_check && hipEventRecord(c.ev[3], s) != hipSuccess) return CDS_HIP_ERROR;
     GetrsCore<float, double> d = g;
     d.B = w.R; d.ldb = n; d.strideB = (int64_t)n * nrhs;
     d.accumulate = 1;
     d.active = w.active;
     st = getrs_core<float, double>(c, d);
     if (st != CDS_SUCCESS) return st;
+    if (prm.host_check) {
+      h_active.resize(batch);
+      if (hipStreamWaitEvent(c.s1, c.ev[3], 0) != hipSuccess) return CDS_HIP_ERROR;
+      if (hipMemcpyAsync(h_active.data(), w.active, sizeof(int) * batch, hipMemcpyDeviceToHost, c.s1) != hipSuccess)
+        return CDS_HIP_ERROR;
+      if (hipStreamSynchronize(c.s1) != hipSuccess) return CDS_HIP_ERROR;
+      bool any = false;
+      for (int v : h_active) any = any || v;
+      if (!any) break;
+    }
   }
   return CDS_SUCCESS;
 }
@@ -762,13 +773,12 @@ cds_status_t gesv_gmres_ir_run(Ctx& c, int prec, int n, const double* A, int64_t
   if (!carve(c.ws, lower, n, 1, 1, 0, w)) return CDS_WORKSPACE_TOO_SMALL;
   if (launch_fill_zero(w.anorm, 8, s) != hipSuccess) return CDS_HIP_ERROR;
   hipLaunchKernelGGL(convert_kernel, dim3((n + 63) / 64, 1), dim3(256), 0, s, A, lda, (int64_t)0, LU, (int64_t)n,
-                     (int64_t)0, n, w.anorm);
+                     (int64_t)0, n, w.anorm, 0, n);
   if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
   Ctx ci = c;
   ci.ws = w.inner; ci.ws_bytes = w.inner_bytes;
-  cds_status_t st = getrf_run_mode<float>(ci, n, LU, n, 0, ipiv, 0, w.info, 1, nb, prec, w.scale);
+  cds_status_t st = getrf_run_mode<float>(ci, n, LU, n, 0, ipiv, 0, w.info, 1, nb, prec, w.scale, w.perm);
   if (st != CDS_SUCCESS) return st;
-  if (launch_perm(ipiv, 0, n, w.perm, n, w.gmap, 1, s) != hipSuccess) return CDS_HIP_ERROR;
   hipLaunchKernelGGL(add_inner_iters_kernel, dim3(1), dim3(1), 0, s, res, (const cds_krylov_result_t*)nullptr, 1);
   return refine(ci, w, 0, 0, n, 1, A, lda, 0, LU, n, 0, w.perm, n, b, n, 0, x, n, 0, prm, res, w.info, 1, &gm);
 }
@@ -835,14 +845,31 @@ cds_status_t gesv_mixed_run(Ctx& c, int prec, int n, int nrhs, const double* A, 
   IrWs w;
   if (!carve(c.ws, c.ws_bytes, n, nrhs, batch, prm.fallback, w, nrhs == 1)) return CDS_WORKSPACE_TOO_SMALL;
   if (launch_fill_zero(w.anorm, batch * 8, s) != hipSuccess) return CDS_HIP_ERROR;
-  hipLaunchKernelGGL(convert_kernel, dim3((n + 63) / 64, batch), dim3(256), 0, s, A, lda, strideA, LU, (int64_t)n,
-                     strideLU, n, w.anorm);
+  // With the look-ahead, the first 1024 columns (at least the first two panels', a panel being at
+  // most 512 wide) are converted first and the rest (with ||A||_inf) on the second stream, beside
+  // the first panel: the factorization's later work on the first stream follows the second
+  // stream's, and the second stream's own work follows it in order.  n > 1024 implies the
+  // factorization takes the look-ahead schedule.
+  const int c1 = std::min(n, 1024);
+  const bool split = c.lookahead && batch == 1 && n > c1;
+  if (split) {
+    hipLaunchKernelGGL(convert_kernel, dim3((n + 63) / 64, 1), dim3(256), 0, s, A, lda, strideA, LU, (int64_t)n,
+                       strideLU, n, (double*)nullptr, 0, c1);
+    if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
+    if (hipEventRecord(c.ev[3], s) != hipSuccess) return CDS_HIP_ERROR;
+    if (hipStreamWaitEvent(c.s1, c.ev[3], 0) != hipSuccess) return CDS_HIP_ERROR;
+    hipLaunchKernelGGL(convert_kernel, dim3((n + 63) / 64, 1), dim3(256), 0, c.s1, A, lda, strideA, LU, (int64_t)n,
+                       strideLU, n, w.anorm, c1, n);
+  } else {
+    hipLaunchKernelGGL(convert_kernel, dim3((n + 63) / 64, batch), dim3(256), 0, s, A, lda, strideA, LU, (int64_t)n,
+                       strideLU, n, w.anorm, 0, n);
+  }
   if (hipGetLastError() != hipSuccess) return CDS_HIP_ERROR;
   Ctx ci = c;
   ci.ws = w.inner; ci.ws_bytes = w.inner_bytes;
-  cds_status_t st = getrf_run_mode<float>(ci, n, LU, n, strideLU, ipiv, strideP, w.info, batch, nb, prec, w.scale);
+  cds_status_t st = getrf_run_mode<float>(ci, n, LU, n, strideLU, ipiv, strideP, w.info, batch, nb, prec, w.scale,
+                                          w.perm);
   if (st != CDS_SUCCESS) return st;
-  if (launch_perm(ipiv, strideP, n, w.perm, n, w.gmap, batch, s) != hipSuccess) return CDS_HIP_ERROR;
   if (w.binv) {
     KScope kb(c.timer, CDS_KC_TRSV, s, 0.0, 0.0);
     if (launch_binv_prep(LU, n, strideLU, n, w.binv, (int64_t)binv_elems(n), batch, s) != hipSuccess)

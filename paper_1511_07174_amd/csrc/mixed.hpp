@@ -5,8 +5,10 @@
 namespace cds {
 
 template <typename T>
+// perm_out (optional, n per matrix): the row order of the factorization (perm[i] = original row at
+// position i), built alongside the interchanges
 cds_status_t getrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int64_t strideA, int32_t* ipiv, int64_t strideP,
-                            int32_t* info, int batch, int nb, int mode, float* scale_part);
+                            int32_t* info, int batch, int nb, int mode, float* scale_part, int32_t* perm_out = nullptr);
 template <typename T>
 cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int nb, int mode, float* scale_part);
 
