@@ -51,9 +51,14 @@ __device__ __forceinline__ void tile_coords(int w, int tiles_m, int tiles_n, int
     t = w;
   }
   if (!lower) {
-    // column-major tile order inside the range: consecutive t share tile_n (B panel) and walk tile_m
-    tm = t % tiles_m;
-    tn = t / tiles_m;
+    // bands of GM tile rows, each walked column by column: the tiles an XCD runs at once (a few
+    // dozen consecutive t) share GM A panels, which stay in its L2 for the whole band, and a
+    // handful of B panels (a plain column-major walk would stream every A panel once per column)
+    constexpr int GM = 16;
+    const int band = t / (GM * tiles_n), r = t - band * GM * tiles_n;
+    const int rows = min(GM, tiles_m - band * GM);
+    tm = band * GM + r % rows;
+    tn = r / rows;
   } else {
     // t -> (tm, tn) with tm >= tn, rows of the lower triangle of tiles
     int r = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
