@@ -5,12 +5,13 @@ persists a JSON table; ``load_table`` installs a table into a handle through
 ``cds_tune`` (the library reads the file).  Tuned quantities:
 
 * ``getrf_nb`` (per dtype, per n bucket): block size of the blocked LU, from
-  {128, 192, 256, 384};
-* ``potrf_nb``: same for Cholesky, from {128, 256, 384};
+  {128, 160, 192, 224, 256, 384, 512}, on the benchmark's uniform systems;
+* ``potrf_nb``: same for Cholesky, from {128, 256, 384, 512}, on the seeded
+  SPD matrices;
 * ``vbatch_tile`` (per n bucket): block-column width of the in-workgroup
   Cholesky of the batched SPD solver, 16 or 32.
 
-Inputs are seeded synthetic matrices of the tuned sizes.  The entry of a size
+Inputs are the seeded synthetic matrices of ``synth`` at the tuned sizes.  The entry of a size
 bucket applies to every n up to the bucket's size; the largest bucket's value
 is repeated for all larger n.  ``handle()`` installs the table shipped with the
 package (``tune_gfx950.json``) when it exists; ``CDS_TUNE_FILE`` names another
@@ -46,16 +47,18 @@ def _timeit(fn, reps=2):
     return best
 
 
-def tune_getrf(sizes=(2048, 4096, 8192, 16384), dtypes=("f64", "f32"), candidates=(128, 160, 192, 224, 256, 384),
-                seed=0):
+def tune_getrf(sizes=(2048, 4096, 8192, 16384), dtypes=("f64", "f32"),
+                candidates=(128, 160, 192, 224, 256, 384, 512), seed=0):
+    """Block size per size bucket, timed on the benchmark's workload: the seeded uniform[-1, 1]
+    systems of synth.uniform_system."""
+    import synth
     h = cds.handle()
     dev = torch.device("cuda", torch.cuda.current_device())
-    g = torch.Generator(device=dev).manual_seed(seed)
     entries, timings = [], []
     for dt in dtypes:
         tdt = torch.float64 if dt == "f64" else torch.float32
         for n in sizes:
-            A = colmajor(torch.rand(n, n, generator=g, device=dev, dtype=tdt) * 2 - 1)
+            A = colmajor(torch.from_numpy(synth.uniform_system(n, 1, seed)[0]).to(dev, tdt))
             LU = torch.empty_like(A)
             ipiv = torch.zeros(n, dtype=torch.int32, device=dev)
             info = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -77,17 +80,16 @@ def tune_getrf(sizes=(2048, 4096, 8192, 16384), dtypes=("f64", "f32"), candidate
     return entries, timings
 
 
-def tune_potrf(sizes=(2048, 4096, 8192, 16384), dtypes=("f64", "f32"), candidates=(128, 256, 384), seed=1):
+def tune_potrf(sizes=(2048, 4096, 8192, 16384), dtypes=("f64", "f32"), candidates=(128, 256, 384, 512), seed=4):
+    """Block size per size bucket on the seeded SPD matrices of synth.spd_matrix."""
+    import synth
     h = cds.handle()
     dev = torch.device("cuda", torch.cuda.current_device())
-    g = torch.Generator(device=dev).manual_seed(seed)
     entries, timings = [], []
     for dt in dtypes:
         tdt = torch.float64 if dt == "f64" else torch.float32
         for n in sizes:
-            M = torch.rand(n, n, generator=g, device=dev, dtype=torch.float64) * 2 - 1
-            A = colmajor((M @ M.T / n + torch.eye(n, device=dev, dtype=torch.float64)).to(tdt))
-            del M
+            A = colmajor(torch.from_numpy(synth.spd_matrix(n, seed)).to(dev, tdt))
             L = torch.empty_like(A)
             info = torch.zeros(1, dtype=torch.int32, device=dev)
             best = None
