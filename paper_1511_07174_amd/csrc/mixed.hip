@@ -561,7 +561,8 @@ static size_t binv_region(int n, int nrhs, int batch, int chol) {
 
 static size_t ir_small_bytes(int n, int nrhs, int batch) {
   return al256(batch * 8) + 2 * al256((size_t)batch * nrhs * 8) + al256(batch * sizeof(IrState)) +
-         al256(batch * 4) + al256((size_t)batch * 4 * 2 * kScaleParts) + al256(batch * 4) + 2 * al256((size_t)batch * n * 4) +
+         al256(batch * 4) + al256((size_t)batch * 4 * 2 * kScaleParts) + al256(batch * 4) + al256((size_t)batch * n * 4) +
+         al256((size_t)batch * perm_moves_ints(n) * 4) +
          al256((size_t)batch * n * nrhs * 8) + al256((size_t)batch * kResChunks * n * 8);
 }
 
@@ -596,7 +597,7 @@ static bool carve(void* ws, size_t ws_bytes, int n, int nrhs, int batch, int fal
   w.scale = (float*)p; p += al256((size_t)batch * 4 * 2 * kScaleParts);
   w.info = (int32_t*)p; p += al256(batch * 4);
   w.perm = (int32_t*)p; p += al256((size_t)batch * n * 4);
-  w.gmap = (int32_t*)p; p += al256((size_t)batch * n * 4);
+  w.gmap = (int32_t*)p; p += al256((size_t)batch * perm_moves_ints(n) * 4);
   w.R = (double*)p; p += al256((size_t)batch * n * nrhs * 8);
   w.part = (double*)p; p += al256((size_t)batch * kResChunks * n * 8);
   if (binv) {

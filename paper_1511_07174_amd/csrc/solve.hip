@@ -69,6 +69,61 @@ __global__ void __launch_bounds__(256) perm_kernel(const int32_t* ipiv0, int64_t
   if (i0 + (int)threadIdx.x < n) perm[i0 + threadIdx.x] = cur;
 }
 
+// The same permutation in two steps, for n up to what one workgroup's LDS holds.
+// perm_chunk_kernel: the interchanges in chunks of PCH; for each chunk, the moves it makes:
+// position p (the chunk's own positions, and partners past the chunk) receives the row that
+// stood at src before the chunk, found by tracing p back through the chunk's interchanges
+// (2 PCH move slots per chunk, unused ones p = -1; a position listed twice moves the same row).
+// perm_apply_kernel: one workgroup applies the chunks' moves in order to the identity, held in
+// LDS: every source of a chunk is read before any of its writes.
+constexpr int PCH = 256;
+constexpr int kPermLdsMax = 32768;   // positions held in LDS by perm_apply_kernel (128 KB)
+__global__ void __launch_bounds__(PCH) perm_chunk_kernel(const int32_t* ipiv0, int64_t strideP, int n, int2* mv0,
+                                                         int64_t strideM) {
+  __shared__ int sp[PCH];
+  const int b = blockIdx.y, c = blockIdx.x, t = threadIdx.x;
+  const int32_t* ipiv = ipiv0 + (size_t)b * strideP;
+  int2* mv = mv0 + (size_t)b * strideM + (size_t)c * 2 * PCH;
+  const int k0 = c * PCH, kc = min(PCH, n - k0);
+  {
+    const int k = k0 + t;
+    const int pv = t < kc ? ipiv[k] - 1 : k;
+    sp[t] = (t < kc && pv > k && pv < n) ? pv : k;   // an invalid entry becomes k <-> k
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int p = h == 0 ? k0 + t : sp[t];
+    const bool cand = t < kc && (h == 0 || p >= k0 + kc);
+    int src = p;
+    for (int i = kc - 1; i >= 0; --i) {
+      const int a = k0 + i, bb = sp[i];
+      src = (src == a) ? bb : ((src == bb) ? a : src);
+    }
+    mv[h * PCH + t] = (cand && src != p) ? make_int2(p, src) : make_int2(-1, -1);
+  }
+}
+
+__global__ void __launch_bounds__(2 * PCH) perm_apply_kernel(const int2* mv0, int64_t strideM, int n, int nchunk,
+                                                             int32_t* perm0, int64_t strideQ) {
+  extern __shared__ int content[];
+  const int b = blockIdx.y, t = threadIdx.x;
+  const int2* mv = mv0 + (size_t)b * strideM;
+  int32_t* perm = perm0 + (size_t)b * strideQ;
+  for (int i = t; i < n; i += 2 * PCH) content[i] = i;
+  int2 nxt = nchunk > 0 ? mv[t] : make_int2(-1, -1);
+  for (int c = 0; c < nchunk; ++c) {
+    const int2 m = nxt;
+    if (c + 1 < nchunk) nxt = mv[(size_t)(c + 1) * 2 * PCH + t];   // one chunk ahead
+    __syncthreads();   // the previous chunk's writes (or the identity) are in place
+    const int v = m.x >= 0 ? content[m.y] : 0;
+    __syncthreads();
+    if (m.x >= 0) content[m.x] = v;
+  }
+  __syncthreads();
+  for (int i = t; i < n; i += 2 * PCH) perm[i] = content[i];
+}
+
 // Y[i, c] = (T) B[src(i), c] with src = perm[i] (gather = 1) or identity; skipped when active[b] == 0
 template <typename S, typename T>
 __global__ void gather_kernel(const S* B0, int64_t ldb, int64_t strideB, T* Y0, int64_t ldy, int64_t strideY,
@@ -427,6 +482,9 @@ constexpr int BB = 128;
 // grid (nblk, 2, batch): block bk of triangle tri (0: L, unit lower; 1: U, upper) of matrix b.
 // Output: D^{-1} then K, each 128 x 128 with element (i, t) at t * 128 + i, zero outside the
 // block's rows and columns (K: outside the dependency's columns; not written without one).
+// D^{-1} by 16 x 16 blocks: the diagonal blocks' inverses by substitution, then block row by
+// block row (from the top for L, from the bottom for U) X_IJ = -X_II sum_K D_IK X_KJ.  K = D^{-1} M
+// on MFMA (16 x 16 x 4 FP32), each wave a 64 x 64 quarter.
 __global__ void __launch_bounds__(256) binv_prep_kernel(const float* M0, int64_t lda, int64_t strideA, int n, int nblk,
                                                         float* out0, int64_t strideO) {
   const int bk = blockIdx.x, tri = blockIdx.y, b = blockIdx.z;
@@ -435,52 +493,104 @@ __global__ void __launch_bounds__(256) binv_prep_kernel(const float* M0, int64_t
   float* K = Dinv + BB * BB;
   __shared__ float D[BB][BB + 1];
   __shared__ float X[BB][BB + 1];
-  const int tid = threadIdx.x;
+  __shared__ float S[7][16][17];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r0 = bk * BB, rb = min(BB, n - r0);
+  // the diagonal block; past the matrix's end the identity (so that the padded part inverts to it)
   for (int e = tid; e < BB * BB; e += 256) {
     const int i = e % BB, t = e / BB;
-    D[i][t] = (i < rb && t < rb) ? M[(r0 + i) + (size_t)(r0 + t) * lda] : 0.f;
+    D[i][t] = (i < rb && t < rb) ? M[(r0 + i) + (size_t)(r0 + t) * lda] : (i == t ? 1.f : 0.f);
+    X[i][t] = 0.f;
   }
   __syncthreads();
-  // column j of D^{-1} by substitution on e_j (thread j); every lane runs the same loop bounds
+  // diagonal 16 x 16 blocks: thread (I, c) solves column c of block I by substitution
   if (tid < BB) {
-    const int j = tid;
+    const int I = tid >> 4, c = tid & 15, o = 16 * I;
     if (tri == 0) {
-      for (int i = 0; i < BB; ++i) {
-        float s = (i == j) ? 1.f : 0.f;
-        for (int t = 0; t < i; ++t) s = fmaf(-D[i][t], X[t][j], s);
-        X[i][j] = (i < rb && j < rb) ? s : 0.f;
+      for (int i = 0; i < 16; ++i) {
+        float s = (i == c) ? 1.f : 0.f;
+        for (int m = 0; m < i; ++m) s = fmaf(-D[o + i][o + m], X[o + m][o + c], s);
+        X[o + i][o + c] = (i >= c) ? s : 0.f;
       }
     } else {
-      for (int i = BB - 1; i >= 0; --i) {
-        float s = (i == j) ? 1.f : 0.f;
-        for (int t = i + 1; t < BB; ++t) s = fmaf(-D[i][t], X[t][j], s);
-        X[i][j] = (i < rb && j < rb) ? s / D[i][i] : 0.f;
+      for (int i = 15; i >= 0; --i) {
+        float s = (i == c) ? 1.f : 0.f;
+        for (int m = i + 1; m < 16; ++m) s = fmaf(-D[o + i][o + m], X[o + m][o + c], s);
+        X[o + i][o + c] = (i <= c) ? s / D[o + i][o + i] : 0.f;
       }
     }
   }
   __syncthreads();
-  for (int e = tid; e < BB * BB; e += 256) Dinv[e] = X[e % BB][e / BB];
+  // off-diagonal blocks, one block row per step
+  for (int st = 1; st < 8; ++st) {
+    const int I = tri == 0 ? st : 7 - st;
+    // S_J = sum over K between J and I (exclusive of I) of D_IK X_KJ, for the st blocks J on I's far side
+    for (int e = tid; e < st * 256; e += 256) {
+      const int jj = e >> 8, r = (e >> 4) & 15, c = e & 15;
+      const int J = tri == 0 ? jj : I + 1 + jj;
+      const int k0 = tri == 0 ? J : I + 1, k1 = tri == 0 ? I : J + 1;   // K in [k0, k1)
+      float acc = 0.f;
+      for (int Kb = k0; Kb < k1; ++Kb)
+#pragma unroll
+        for (int m = 0; m < 16; ++m) acc = fmaf(D[16 * I + r][16 * Kb + m], X[16 * Kb + m][16 * J + c], acc);
+      S[jj][r][c] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < st * 256; e += 256) {
+      const int jj = e >> 8, r = (e >> 4) & 15, c = e & 15;
+      const int J = tri == 0 ? jj : I + 1 + jj;
+      float acc = 0.f;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) acc = fmaf(X[16 * I + r][16 * I + m], S[jj][m][c], acc);
+      X[16 * I + r][16 * J + c] = -acc;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < BB * BB; e += 256) {
+    const int i = e % BB, t = e / BB;
+    Dinv[e] = (i < rb && t < rb) ? X[i][t] : 0.f;
+  }
   const int dep = tri == 0 ? bk - 1 : bk + 1;
   if (dep < 0 || dep >= nblk) return;   // uniform over the workgroup
   const int c0 = dep * BB, cw = min(BB, n - c0);
+  __syncthreads();   // D is free (the inverse is complete)
   for (int e = tid; e < BB * BB; e += 256) {
     const int u = e % BB, t = e / BB;
     D[u][t] = (u < rb && t < cw) ? M[(r0 + u) + (size_t)(c0 + t) * lda] : 0.f;
   }
-  __syncthreads();
-  // thread (i, h): K(i, t) = sum_u D^{-1}(i, u) M(u, t) for t in [64 h, 64 h + 64), u ascending
-  const int i = tid % BB, t0 = (tid / BB) * 64;
-  float acc[64];
-#pragma unroll
-  for (int t = 0; t < 64; ++t) acc[t] = 0.f;
-  for (int u = 0; u < BB; ++u) {
-    const float xi = X[i][u];
-#pragma unroll
-    for (int t = 0; t < 64; ++t) acc[t] = fmaf(xi, D[u][t0 + t], acc[t]);
+  for (int e = tid; e < BB * BB; e += 256) {   // rows and columns of X past the block's end count as zero
+    const int i = e % BB, t = e / BB;
+    if (i >= rb || t >= rb) X[i][t] = 0.f;
   }
+  __syncthreads();
+  // K = X D on MFMA: wave w takes rows 64 (w & 1) .., columns 64 (w >> 1) .., as 4 x 4 blocks of 16 x 16
+  const int wr = (wave & 1) * 64, wc = (wave >> 1) * 64;
+  f4 acc[4][4];
 #pragma unroll
-  for (int t = 0; t < 64; ++t) K[(size_t)(t0 + t) * BB + i] = acc[t];
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = (f4){0.f, 0.f, 0.f, 0.f};
+  for (int u0 = 0; u0 < BB; u0 += 4) {
+    float af[4], bf[4];
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi) af[mi] = X[wr + mi * 16 + (lane & 15)][u0 + (lane >> 4)];
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni) bf[ni] = D[u0 + (lane >> 4)][wc + ni * 16 + (lane & 15)];
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[mi], bf[ni], acc[mi][ni], 0, 0, 0);
+  }
+  // accumulator v of block (mi, ni): row wr + 16 mi + 4 (lane / 16) + v, column wc + 16 ni + (lane & 15)
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = wr + mi * 16 + 4 * (lane >> 4) + v, t = wc + ni * 16 + (lane & 15);
+        K[(size_t)t * BB + i] = acc[mi][ni][v];
+      }
 }
 
 struct BinvArgs {
@@ -515,6 +625,7 @@ __global__ void __launch_bounds__(TNT, 1) trsv1_binv_kernel(BinvArgs a) {
   __shared__ float sv[BB];
   __shared__ float red[2][BB];
   __shared__ float red2[2][BB];
+  __shared__ __attribute__((aligned(16))) float sy[4][64];
   if (tid == 0) s_ticket = atomicAdd(a.tickets + b, 1);
   __syncthreads();
   const int lb = s_ticket;
@@ -605,13 +716,18 @@ __global__ void __launch_bounds__(TNT, 1) trsv1_binv_kernel(BinvArgs a) {
     const bool v[1] = {idx < a.n};
     float y[1];
     ll_wait_vals<float, 1>(p, v, a.flag, a.err, y);
+    // x_p's 64 values of this wave go through LDS and come back as 16-byte broadcast reads (every
+    // lane reads the same address), in place of 64 cross-lane reads
+    sy[q][lane] = y[0];
+    wave_fence();
     float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
 #pragma unroll
     for (int t = 0; t < 64; t += 4) {
-      p0 = fmaf(sK[ch * 64 + t][row], lane_bcast(y[0], t), p0);
-      p1 = fmaf(sK[ch * 64 + t + 1][row], lane_bcast(y[0], t + 1), p1);
-      p2 = fmaf(sK[ch * 64 + t + 2][row], lane_bcast(y[0], t + 2), p2);
-      p3 = fmaf(sK[ch * 64 + t + 3][row], lane_bcast(y[0], t + 3), p3);
+      const f4 yv = *reinterpret_cast<const f4*>(&sy[q][t]);
+      p0 = fmaf(sK[ch * 64 + t][row], yv[0], p0);
+      p1 = fmaf(sK[ch * 64 + t + 1][row], yv[1], p1);
+      p2 = fmaf(sK[ch * 64 + t + 2][row], yv[2], p2);
+      p3 = fmaf(sK[ch * 64 + t + 3][row], yv[3], p3);
     }
     red2[ch][row] = (p0 + p1) + (p2 + p3);
     __syncthreads();
@@ -658,17 +774,28 @@ hipError_t launch_binv_prep(const float* LU, int64_t lda, int64_t strideA, int n
 size_t getrs_ws_bytes(int n, int nrhs, int batch, size_t elem) {
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   size_t perm = al((size_t)batch * n * 4);
-  size_t gmap = al((size_t)batch * n * 4);
+  size_t gmap = al((size_t)batch * perm_moves_ints(n) * 4);
   size_t temp = al((size_t)batch * n * std::max(nrhs, 1) * elem);
   size_t slots = al(trsv_slot_bytes(n, nrhs, batch, elem));
   size_t tick = al((size_t)batch * 64 * 4);
   return kErrRegion + perm + gmap + temp + slots + tick;
 }
 
+size_t perm_moves_ints(int n) { return (size_t)((std::max(n, 1) + PCH - 1) / PCH) * 2 * PCH * 2; }
+
 hipError_t launch_perm(const int32_t* ipiv, int64_t strideP, int n, int32_t* perm, int64_t strideQ, int32_t* gmap,
                        int batch, hipStream_t s) {
-  (void)gmap;
   if (n <= 0 || batch <= 0) return hipSuccess;
+  if (gmap != nullptr && n <= kPermLdsMax) {
+    // chunked: gmap holds perm_moves_ints(n) ints per matrix
+    const int nchunk = (n + PCH - 1) / PCH;
+    const int64_t strideM = (int64_t)perm_moves_ints(n) / 2;
+    int2* mv = reinterpret_cast<int2*>(gmap);
+    hipLaunchKernelGGL(perm_chunk_kernel, dim3(nchunk, batch), dim3(PCH), 0, s, ipiv, strideP, n, mv, strideM);
+    hipLaunchKernelGGL(perm_apply_kernel, dim3(1, batch), dim3(2 * PCH), (size_t)n * 4, s, (const int2*)mv, strideM,
+                       n, nchunk, perm, strideQ);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(perm_kernel, dim3((n + 255) / 256, batch), dim3(256), 0, s, ipiv, strideP, n, perm, strideQ);
   return hipGetLastError();
 }
@@ -682,7 +809,7 @@ cds_status_t getrs_core(Ctx& c, const GetrsCore<T, S>& g) {
   int32_t* perm = (int32_t*)base;
   base += al((size_t)batch * n * 4);
   int32_t* gmap = (int32_t*)base;
-  base += al((size_t)batch * n * 4);
+  base += al((size_t)batch * perm_moves_ints(n) * 4);
   T* temp = (T*)base;
   base += al((size_t)batch * n * nrhs * sizeof(T));
   uint64_t* slots = (uint64_t*)base;

@@ -35,6 +35,9 @@ size_t trsv_slot_bytes(int n, int nrhs, int batch, size_t elem);
 size_t binv_elems(int n);
 hipError_t launch_binv_prep(const float* LU, int64_t lda, int64_t strideA, int n, float* out, int64_t strideO,
                             int batch, hipStream_t s);
+// Row order of LAPACK interchanges (perm[i] = original row at position i).  gmap: scratch of
+// perm_moves_ints(n) ints per matrix for the chunked method, or null for the per-position trace.
+size_t perm_moves_ints(int n);
 hipError_t launch_perm(const int32_t* ipiv, int64_t strideP, int n, int32_t* perm, int64_t strideQ, int32_t* gmap,
                        int batch, hipStream_t s);
 
