@@ -284,7 +284,7 @@ cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int
   nb = std::min(512, std::max(SB, (nb / SB) * SB));
   double* linv = (double*)((char*)c.ws + kErrRegion);
   // the diagonal block of block column k, L21 below it, and (mode 2) the operand scale
-  auto panel = [&](int k, int jb, hipStream_t st) -> cds_status_t {
+  auto panel = [&](int k, int jb, int par, hipStream_t st) -> cds_status_t {
     {
       KScope ks(c.timer, CDS_KC_PANEL, st, (double)jb * jb * jb / 3.0, (double)jb * jb * sizeof(T));
       if (jb <= PJB) {
@@ -309,42 +309,82 @@ cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int
     }
     if (mode == 2 && scale_part != nullptr) {
       if constexpr (std::is_same<T, float>::value) {
-        if (launch_maxabs_part(A + (k + jb) + (size_t)k * lda, lda, 0, rem, jb, scale_part, 1, st) != hipSuccess)
+        if (launch_maxabs_part(A + (k + jb) + (size_t)k * lda, lda, 0, rem, jb, scale_part + (size_t)par * kScaleParts, 1,
+                               st) != hipSuccess)
           return CDS_HIP_ERROR;
       }
     }
     return CDS_SUCCESS;
   };
-  // A[r0:n, c0:c1] -= L21(r0:n) L21(c0:c1)^T, lower tiles only (L21 = A[k+jb:n, k:k+jb])
-  auto update = [&](int k, int jb, int r0, int c0, int c1, hipStream_t st) -> cds_status_t {
-    const int m = n - r0, nn = c1 - c0;
+  // A[r0:r1, c0:c1] -= L21(r0:r1) L21(c0:c1)^T with L21 = A[k+jb:n, k:k+jb]; lower: only the tiles on
+  // or below the diagonal (r0 == c0, r1 == c1).  par: the operand-scale region of block column k.
+  auto syrk = [&](int k, int jb, int r0, int r1, int c0, int c1, bool lower, int par,
+                  hipStream_t st) -> cds_status_t {
+    const int m = r1 - r0, nn = c1 - c0;
     if (m <= 0 || nn <= 0) return CDS_SUCCESS;
     GemmArgs<T> g;
     g.m = m; g.n = nn; g.k = jb;
     g.A = A + r0 + (size_t)k * lda; g.lda = lda; g.strideA = 0;
     g.B = A + c0 + (size_t)k * lda; g.ldb = lda; g.strideB = 0;
     g.C = A + r0 + (size_t)c0 * lda; g.ldc = lda; g.strideC = 0;
-    g.alpha = (T)-1; g.transB = 1; g.lower = 1; g.scale_part = nullptr; g.scaleA = 0;
+    g.alpha = (T)-1; g.transB = 1; g.lower = lower ? 1 : 0; g.scale_part = nullptr; g.scaleA = 0;
     g.guard = info;
     if (mode == 2 && scale_part != nullptr) {
-      g.scale_part = scale_part;
+      g.scale_part = scale_part + (size_t)par * kScaleParts;
       g.scaleA = 1;   // A and B are both L21
     }
-    KScope ks(c.timer, CDS_KC_UPDATE, st, (double)m * nn * jb * 2.0 - (double)nn * nn * jb,
+    KScope ks(c.timer, CDS_KC_UPDATE, st, lower ? (double)m * nn * jb * 2.0 - (double)nn * nn * jb : 2.0 * m * nn * jb,
               (double)sizeof(T) * ((double)m * nn + (double)(m + nn) * jb));
     return launch_gemm<T>(g, 1, mode, st) == hipSuccess ? CDS_SUCCESS : CDS_HIP_ERROR;
   };
-  // Right-looking, in stream order.  (A two-stream look-ahead, as in getrf, measured slower here: the
-  // trailing update keeps two workgroups on every CU, so the one-workgroup diagonal-block kernel
-  // only starts when the update drains and the extra next-column launch is pure overhead.)
-  for (int k = 0; k < n; k += nb) {
-    const int jb = std::min(nb, n - k);
-    cds_status_t st = panel(k, jb, s);
-    if (st != CDS_SUCCESS) return st;
-    if (n - k - jb <= 0) break;
-    st = update(k, jb, k + jb, k + jb, n, s);
-    if (st != CDS_SUCCESS) return st;
+  const bool la = c.lookahead && n > nb;
+  if (!la) {
+    // right-looking, in stream order
+    for (int k = 0, step = 0; k < n; k += nb, ++step) {
+      const int jb = std::min(nb, n - k);
+      cds_status_t st = panel(k, jb, step & 1, s);
+      if (st != CDS_SUCCESS) return st;
+      if (n - k - jb <= 0) break;
+      st = syrk(k, jb, k + jb, n, k + jb, n, true, step & 1, s);
+      if (st != CDS_SUCCESS) return st;
+    }
+    return CDS_SUCCESS;
   }
+  // Look-ahead, as in getrf: the first stream updates the next block column (its diagonal block
+  // and the rows below it), then factors it (diagonal block, TRSM); the second stream updates the
+  // rest of the trailing matrix meanwhile.  The next block column's update waits for the previous
+  // rest update, which reached its columns.
+  hipStream_t s1 = c.s1;
+  hipEvent_t evL = c.ev[1], evR = c.ev[2];
+  if (hipEventRecord(c.ev[0], s) != hipSuccess) return CDS_HIP_ERROR;
+  if (hipStreamWaitEvent(s1, c.ev[0], 0) != hipSuccess) return CDS_HIP_ERROR;
+  cds_status_t st = panel(0, std::min(nb, n), 0, s);
+  if (st != CDS_SUCCESS) return st;
+  bool have_rest = false;
+  for (int k = 0, step = 0; k < n; k += nb, ++step) {
+    const int jb = std::min(nb, n - k), par = step & 1;
+    const int kn = k + jb, jbn = std::min(nb, n - kn);
+    if (jbn > 0) {
+      if (have_rest && hipStreamWaitEvent(s, evR, 0) != hipSuccess) return CDS_HIP_ERROR;
+      st = syrk(k, jb, kn, kn + jbn, kn, kn + jbn, true, par, s);   // the next diagonal block
+      if (st != CDS_SUCCESS) return st;
+      st = syrk(k, jb, kn + jbn, n, kn, kn + jbn, false, par, s);  // the rows below it
+      if (st != CDS_SUCCESS) return st;
+    }
+    if (hipEventRecord(evL, s) != hipSuccess) return CDS_HIP_ERROR;
+    if (jbn > 0) {
+      st = panel(kn, jbn, par ^ 1, s);
+      if (st != CDS_SUCCESS) return st;
+    }
+    if (hipStreamWaitEvent(s1, evL, 0) != hipSuccess) return CDS_HIP_ERROR;
+    if (jbn > 0) {
+      st = syrk(k, jb, kn + jbn, n, kn + jbn, n, true, par, s1);
+      if (st != CDS_SUCCESS) return st;
+    }
+    if (hipEventRecord(evR, s1) != hipSuccess) return CDS_HIP_ERROR;
+    have_rest = true;
+  }
+  if (hipStreamWaitEvent(s, evR, 0) != hipSuccess) return CDS_HIP_ERROR;
   return CDS_SUCCESS;
 }
 
