@@ -115,41 +115,90 @@ __device__ __forceinline__ T lane_get(T v, int l) {
   }
 }
 
-// jb <= 128: the whole diagonal block lives in LDS (column-major, ld 129) for the
-// duration of the kernel; it is read from and written to global memory once.  Per
-// 32-wide sub-block: (a) one wave factors the sub-block's diagonal with row r in
-// lane r (registers), column j broadcast through LDS, division by L(j,j) so that
-// exact data stays exact; (b) the rows below in the block are solved against it,
-// one row per thread, with the reciprocal of the diagonal; (c) the rest of the
-// block gets the symmetric rank-32 update on MFMA tiles.
-constexpr int PJB = 128, PLD = PJB + 1;
+// Column c of the inverse of the lower-triangular 16 x 16 block at (r0, r0) of the LDS block
+// (ld PLD), in FP64, by forward substitution: the same operations as diag_inv16_column, as
+// straight-line code (the terms q < c multiply y[q] = 0 and leave the sum as it is).  EDGE: rows
+// at or beyond jb act as the identity (they read row jb - 1, and the result is replaced).
+template <typename T, bool EDGE, int LD>
+__device__ __forceinline__ void inv16_column_ld(const T* Ds, int r0, int jb, int c, double (&y)[16]) {
+  // row i of the block is read while row i - 1 is being solved
+  T row[2][16];
+  auto load_row = [&](T (&dst)[16], int i) {
+    const int ri = EDGE ? min(r0 + i, jb - 1) : r0 + i;
+#pragma unroll
+    for (int q = 0; q <= i; ++q) dst[q] = Ds[(r0 + q) * LD + ri];
+  };
+  load_row(row[0], 0);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    if (i + 1 < 16) load_row(row[(i + 1) & 1], i + 1);
+    const T(&Lr)[16] = row[i & 1];
+    double s = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = 0; q < i; ++q) s -= (double)Lr[q] * y[q];
+    const double yi = s / (double)Lr[i];
+    y[i] = (EDGE && r0 + i >= jb) ? ((i == c) ? 1.0 : 0.0) : (i < c ? 0.0 : yi);
+  }
+}
+
+// jb <= 128: the whole diagonal block lives in LDS (column-major, ld 130 for FP64 and
+// 132 for FP32, so that every column starts on 16 bytes) for the duration of the
+// kernel; its columns arrive by direct global-to-LDS loads (the upper triangle comes
+// along and is never read) and the lower triangle is written back once.  Per 32-wide sub-block:
+//   (a) one wave factors the sub-block's diagonal with row r in lane r (registers).
+//       The entries of column j that the later columns need come from the other
+//       lanes by readlane, the next column's first, so that a column's dependent
+//       chain is its square root, one division (by L(j,j), which keeps exact data
+//       exact) and one update.  The same wave then inverts the sub-block's two
+//       16 x 16 diagonal blocks in FP64, column by column;
+//   (b) the rows below it in the block, X = A_below L^{-T}, by 16 x 16 blocks on
+//       MFMA tiles: X0 = B0 inv(L00)^T, B1 -= X0 L10^T, X1 = B1 inv(L11)^T;
+//   (c) the rest of the block gets the symmetric rank-32 update on MFMA tiles.
+// The 16 x 16 inverses are also the ones the TRSM below the block uses.
+constexpr int PJB = 128;
 
 template <typename T>
 __global__ void __launch_bounds__(256) potf2_lds_kernel(T* A, int64_t lda, int k, int jb, int32_t* info,
                                                         double* linv) {
-  __shared__ T Ds[PJB * PLD];   // (r, c) at Ds[c * PLD + r]
-  __shared__ T colb[64];
-  __shared__ T rdiag[SB];
+  constexpr bool F64 = std::is_same<T, double>::value;
+  typedef typename std::conditional<F64, d4, f4>::type acc_t;
+  constexpr int PLD = PJB + (F64 ? 2 : 4);
+  __shared__ __align__(16) T Ds[PJB * PLD];   // (r, c) at Ds[c * PLD + r]
+  __shared__ double Iv[2][16][17];   // inverses of the sub-block's 16 x 16 diagonal blocks, (i, c) at Iv[b][i][c]
   __shared__ int s_fail;
   if (*info != 0) return;
   T* D = A + k + (size_t)k * lda;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // 16 loads in flight per thread (the block is jb x jb, at most 64 elements per thread)
-  for (int base = 0; base < jb * jb; base += 16 * 256) {
-    T v[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = base + u * 256 + tid, r = idx % jb, c = idx / jb;
-      v[u] = (idx < jb * jb && r >= c) ? D[r + (size_t)c * lda] : (T)0;
+  // wave w loads columns w, w + 4, ...: a column in 16-byte pieces, one per lane, where its bytes
+  // are a multiple of 16 and start on 16 bytes; else as 4-byte words, 64 per instruction
+  {
+    const bool v16 = (jb * (int)sizeof(T)) % 16 == 0 && (uintptr_t)D % 16 == 0 && (lda * (int64_t)sizeof(T)) % 16 == 0;
+    if (v16) {
+      const int nq = jb * (int)sizeof(T) / 16;
+      for (int c = wave; c < jb; c += 4)
+        if (lane < nq)
+          __builtin_amdgcn_global_load_lds((const void*)(reinterpret_cast<const char*>(D + (size_t)c * lda) + 16 * lane),
+                                           (void*)(Ds + c * PLD), 16, 0, 0);
+    } else {
+      const int nw = jb * (int)(sizeof(T) / 4);
+      for (int c = wave; c < jb; c += 4) {
+        const char* src = reinterpret_cast<const char*>(D + (size_t)c * lda);
+        char* dst = reinterpret_cast<char*>(Ds + c * PLD);
+        for (int w0 = 0; w0 < nw; w0 += 64)
+          if (w0 + lane < nw)
+            __builtin_amdgcn_global_load_lds((const void*)(src + 4 * (w0 + lane)), (void*)(dst + 4 * w0), 4, 0, 0);
+      }
     }
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int idx = base + u * 256 + tid;
-      if (idx < jb * jb) Ds[(idx / jb) * PLD + idx % jb] = v[u];
-    }
+    // the direct loads into LDS count as vector memory loads
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
   }
   if (tid == 0) s_fail = 0;
   __syncthreads();
+  // MFMA operand and accumulator positions (16 x 16 x 4 tiles): at k-step s, lane l supplies k index
+  // kidx(s, l / 16); accumulator v of lane l is element (kidx(v, l / 16), l % 16) of the result, so a
+  // product's accumulators are the next product's B operand as they stand
+  const int li = lane & 15, kl = lane >> 4;
+  auto kidx = [&](int s) { return F64 ? 4 * s + kl : 4 * kl + s; };
   for (int s0 = 0; s0 < jb; s0 += SB) {
     const int sw = min(SB, jb - s0);
     // (a) the sub-block's diagonal
@@ -161,109 +210,165 @@ __global__ void __launch_bounds__(256) potf2_lds_kernel(T* A, int64_t lda, int k
 #pragma unroll
       for (int c = 0; c < SB; ++c)
         v[c] = r < sw ? (c <= r && c < sw ? Ds[(s0 + c) * PLD + s0 + r] : (T)0) : (c == r ? (T)1 : (T)0);
+      // column j: its pivot d = a_jj minus the updates of the previous columns, L(j,j) = sqrt(d)
+      // and the rows below divided by it; the source order puts the next column's pivot chain ahead
+      // of the rest of the current column's update (each v[c] still takes the columns in order)
       int fail = 0;
-#pragma unroll
-      for (int j = 0; j < SB; ++j) {
-        const T d = lane_get(v[j], j);   // a_jj minus the updates of the previous columns
-        if (fail == 0 && !(d > (T)0)) fail = j + 1;
+      T lj;
+      {
+        const T d = lane_get(v[0], 0);
+        if (!(d > (T)0)) fail = 1;
         const T ljj = sqrt_t(d);
-        v[j] = (r == j) ? ljj : (r > j ? v[j] / ljj : (T)0);
-        colb[r] = v[j];
-        wave_fence();
+        lj = (r == 0) ? ljj : (r > 0 ? v[0] / ljj : (T)0);
+        v[0] = lj;
+      }
 #pragma unroll
-        for (int c = j + 1; c < SB; ++c) v[c] -= v[j] * colb[c];
-        wave_fence();
+      for (int j = 0; j + 1 < SB; ++j) {
+        v[j + 1] -= lj * lane_get(lj, j + 1);
+        const T d = lane_get(v[j + 1], j + 1);
+        if (fail == 0 && !(d > (T)0)) fail = j + 2;
+        const T ljj = sqrt_t(d);
+        const T ln = (r == j + 1) ? ljj : (r > j + 1 ? v[j + 1] / ljj : (T)0);
+        // entries above the diagonal (c > r) take junk here; they are zeroed at step c and never stored
+#pragma unroll
+        for (int c = j + 2; c < SB; ++c) v[c] -= lj * lane_get(lj, c);
+        v[j + 1] = ln;
+        lj = ln;
       }
       if (fail) {
         if (lane == 0) {
           s_fail = 1;
           atomicCAS(info, 0, k + s0 + fail);
         }
-      } else if (r < sw) {
+      } else {
+        if (r < sw) {
 #pragma unroll
-        for (int c = 0; c < SB; ++c)
-          if (c <= r) Ds[(s0 + c) * PLD + s0 + r] = v[c];
-        T vr = (T)1;
+          for (int c = 0; c < SB; ++c)
+            if (c <= r) Ds[(s0 + c) * PLD + s0 + r] = v[c];
+        }
+        wave_fence();   // the inverses read entries stored by other lanes of this wave
+        // lane c: column c % 16 of the inverse of diagonal block c / 16; rows at or beyond jb act as
+        // the identity
+        if (lane < 32) {
+          const int bb = lane >> 4, cc = lane & 15, r0 = s0 + 16 * bb;
+          double y[16];
+          if (s0 + SB <= jb) inv16_column_ld<T, false, PLD>(Ds, r0, jb, cc, y);
+          else inv16_column_ld<T, true, PLD>(Ds, r0, jb, cc, y);
 #pragma unroll
-        for (int c = 0; c < SB; ++c) vr = (c == r) ? v[c] : vr;
-        rdiag[r] = (T)1 / vr;
+          for (int i = 0; i < 16; ++i) Iv[bb][i][cc] = y[i];
+          if (linv != nullptr && r0 < jb) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) linv[(size_t)(r0 / 16) * 256 + i * 16 + cc] = y[i];
+          }
+        }
       }
     }
     __syncthreads();
     if (s_fail) break;
-    // (b) rows below the sub-block: x L11^T = a; the dot products in four independent partial
-    // sums, the diagonal applied as a precomputed reciprocal (no division on the chain)
-    const int rem = jb - s0 - sw;
-    for (int t = tid; t < rem; t += 256) {
-      const int i = s0 + sw + t;
-      T x[SB];
+    const int rem = jb - s0 - sw;   // rem > 0 only below a full sub-block
+    // (b) rows below the sub-block, one 16-row tile per wave at a time
+    for (int ti = wave; 16 * ti < rem; ti += 4) {
+      const int R = s0 + SB + 16 * ti;   // first row of the tile
+      const bool rin = R + li < jb;
+      acc_t x0, b1, x1;
 #pragma unroll
-      for (int c = 0; c < SB; ++c) x[c] = c < sw ? Ds[(s0 + c) * PLD + i] : (T)0;
+      for (int v = 0; v < 4; ++v) {
+        x0[v] = (T)0;
+        x1[v] = (T)0;
+        b1[v] = rin ? Ds[(s0 + 16 + kidx(v)) * PLD + R + li] : (T)0;
+      }
+      // X0 = B0 inv(L00)^T (element (j, i) of the product is X0(i, j))
 #pragma unroll
-      for (int c = 0; c < SB; ++c) {
-        if (c < sw) {
-          T p0 = (T)0, p1 = (T)0, p2 = (T)0, p3 = (T)0;
+      for (int s = 0; s < 4; ++s) {
+        const T p = (T)Iv[0][li][kidx(s)];
+        const T q = rin ? Ds[(s0 + kidx(s)) * PLD + R + li] : (T)0;
+        if constexpr (F64) x0 = __builtin_amdgcn_mfma_f64_16x16x4f64(p, q, x0, 0, 0, 0);
+        else x0 = __builtin_amdgcn_mfma_f32_16x16x4f32(p, q, x0, 0, 0, 0);
+      }
+      // B1 -= X0 L10^T
 #pragma unroll
-          for (int u = 0; u + 3 < c; u += 4) {
-            p0 += x[u] * Ds[(s0 + u) * PLD + s0 + c];
-            p1 += x[u + 1] * Ds[(s0 + u + 1) * PLD + s0 + c];
-            p2 += x[u + 2] * Ds[(s0 + u + 2) * PLD + s0 + c];
-            p3 += x[u + 3] * Ds[(s0 + u + 3) * PLD + s0 + c];
-          }
+      for (int s = 0; s < 4; ++s) {
+        const T p = -Ds[(s0 + kidx(s)) * PLD + s0 + 16 + li];
+        if constexpr (F64) b1 = __builtin_amdgcn_mfma_f64_16x16x4f64(p, x0[s], b1, 0, 0, 0);
+        else b1 = __builtin_amdgcn_mfma_f32_16x16x4f32(p, x0[s], b1, 0, 0, 0);
+      }
+      // X1 = B1 inv(L11)^T
 #pragma unroll
-          for (int u = c & ~3; u < c; ++u) p0 += x[u] * Ds[(s0 + u) * PLD + s0 + c];
-          x[c] = (x[c] - ((p0 + p1) + (p2 + p3))) * rdiag[c];
+      for (int s = 0; s < 4; ++s) {
+        const T p = (T)Iv[1][li][kidx(s)];
+        if constexpr (F64) x1 = __builtin_amdgcn_mfma_f64_16x16x4f64(p, b1[s], x1, 0, 0, 0);
+        else x1 = __builtin_amdgcn_mfma_f32_16x16x4f32(p, b1[s], x1, 0, 0, 0);
+      }
+      if (rin) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          Ds[(s0 + kidx(v)) * PLD + R + li] = x0[v];
+          Ds[(s0 + 16 + kidx(v)) * PLD + R + li] = x1[v];
         }
       }
-#pragma unroll
-      for (int c = 0; c < SB; ++c)
-        if (c < sw) Ds[(s0 + c) * PLD + i] = x[c];
     }
     __syncthreads();
-    // (c) trailing part of the block on MFMA: 16 x 16 tiles (ti >= tc) of the lower triangle, one
-    // tile per wave at a time, D = P_rows P_cols^T with P = the sub-block's columns below it
+    // (c) trailing part of the block on MFMA: 16 x 16 tiles (ti >= tc) of the lower triangle,
+    // D = P_rows P_cols^T with P = the sub-block's columns below it
     {
-      constexpr bool F64 = std::is_same<T, double>::value;
-      typedef typename std::conditional<F64, d4, f4>::type acc_t;
       const int b0 = s0 + sw, nt = (rem + 15) / 16, ntiles = nt * (nt + 1) / 2;
-      const int li = lane & 15, lg = lane >> 4;
-      for (int tile = wave; tile < ntiles; tile += 4) {
+      const int lg = kl;
+      auto coords = [&](int tile, int& i0, int& c0) {
         int ti = (int)((sqrtf(8.0f * tile + 1.0f) - 1.0f) * 0.5f);
         while (ti * (ti + 1) / 2 > tile) --ti;
         while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
-        const int tc = tile - ti * (ti + 1) / 2;
-        const int i0 = b0 + 16 * ti, c0 = b0 + 16 * tc;
-        acc_t acc;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[v] = (T)0;
-#pragma unroll
-        for (int k4 = 0; k4 < SB; k4 += 4) {
-          const int kk = k4 + lg;
-          const T a = (kk < sw && i0 + li < jb) ? Ds[(s0 + kk) * PLD + i0 + li] : (T)0;
-          const T b = (kk < sw && c0 + li < jb) ? Ds[(s0 + kk) * PLD + c0 + li] : (T)0;
-          if constexpr (F64)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-          else
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
-        }
+        i0 = b0 + 16 * ti;
+        c0 = b0 + 16 * (tile - ti * (ti + 1) / 2);
+      };
+      auto finish = [&](const acc_t& acc, int i0, int c0) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = i0 + (F64 ? (lg + 4 * v) : (4 * lg + v)), c = c0 + li;
           if (i < jb && c <= i) Ds[c * PLD + i] -= acc[v];
         }
+      };
+      // two tiles per wave at a time, so that two independent MFMA chains share the k-loop
+      for (int t0 = wave; t0 < ntiles; t0 += 8) {
+        const bool two = t0 + 4 < ntiles;
+        int i0a, c0a, i0b, c0b;
+        coords(t0, i0a, c0a);
+        coords(two ? t0 + 4 : t0, i0b, c0b);
+        acc_t acc0, acc1;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          acc0[v] = (T)0;
+          acc1[v] = (T)0;
+        }
+#pragma unroll
+        for (int k4 = 0; k4 < SB; k4 += 4) {
+          const int kk = k4 + lg;
+          const T a0 = (kk < sw && i0a + li < jb) ? Ds[(s0 + kk) * PLD + i0a + li] : (T)0;
+          const T b0v = (kk < sw && c0a + li < jb) ? Ds[(s0 + kk) * PLD + c0a + li] : (T)0;
+          const T a1 = (kk < sw && i0b + li < jb) ? Ds[(s0 + kk) * PLD + i0b + li] : (T)0;
+          const T b1v = (kk < sw && c0b + li < jb) ? Ds[(s0 + kk) * PLD + c0b + li] : (T)0;
+          if constexpr (F64) {
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0v, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1v, acc1, 0, 0, 0);
+          } else {
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0v, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1v, acc1, 0, 0, 0);
+          }
+        }
+        finish(acc0, i0a, c0a);
+        if (two) finish(acc1, i0b, c0b);
       }
     }
     __syncthreads();
   }
   // the factored (or, after a failed pivot, partially factored) lower triangle back to A
-  for (int idx = tid; idx < jb * jb; idx += 256) {
-    const int r = idx % jb, c = idx / jb;
-    if (r >= c) D[r + (size_t)c * lda] = Ds[c * PLD + r];
+#pragma unroll 4
+  for (int c = wave; c < jb; c += 4) {
+#pragma unroll
+    for (int q = 0; q < PJB / 64; ++q) {
+      const int r = 64 * q + lane;
+      if (r >= c && r < jb) D[r + (size_t)c * lda] = Ds[c * PLD + r];
+    }
   }
-  // the inverses of the factor's 16 x 16 diagonal blocks for the TRSM below it, from the block in LDS
-  // (after a failed pivot the TRSM does not run and these are never read)
-  if (linv != nullptr)
-    for (int t = tid; t < ((jb + 15) / 16) * 16; t += 256) diag_inv16_column<T, false>(Ds, PLD, jb, t >> 4, t & 15, linv);
 }
 
 }  // namespace
