@@ -421,8 +421,8 @@ cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int
     }
     return CDS_SUCCESS;
   };
-  // A[r0:r1, c0:c1] -= L21(r0:r1) L21(c0:c1)^T with L21 = A[k+jb:n, k:k+jb]; lower: only the tiles on
-  // or below the diagonal (r0 == c0, r1 == c1).  par: the operand-scale region of block column k.
+  // A[r0:r1, c0:c1] -= L21(r0:r1) L21(c0:c1)^T with L21 = A[k+jb:n, k:k+jb]; lower: only the entries on
+  // or below the diagonal (r0 == c0, r1 >= c1).  par: the operand-scale region of block column k.
   auto syrk = [&](int k, int jb, int r0, int r1, int c0, int c1, bool lower, int par,
                   hipStream_t st) -> cds_status_t {
     const int m = r1 - r0, nn = c1 - c0;
@@ -471,9 +471,7 @@ cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int
     const int kn = k + jb, jbn = std::min(nb, n - kn);
     if (jbn > 0) {
       if (have_rest && hipStreamWaitEvent(s, evR, 0) != hipSuccess) return CDS_HIP_ERROR;
-      st = syrk(k, jb, kn, kn + jbn, kn, kn + jbn, true, par, s);   // the next diagonal block
-      if (st != CDS_SUCCESS) return st;
-      st = syrk(k, jb, kn + jbn, n, kn, kn + jbn, false, par, s);  // the rows below it
+      st = syrk(k, jb, kn, n, kn, kn + jbn, true, par, s);   // the next diagonal block and the rows below it
       if (st != CDS_SUCCESS) return st;
     }
     if (hipEventRecord(evL, s) != hipSuccess) return CDS_HIP_ERROR;

@@ -37,10 +37,15 @@ template <> struct GemmCfg<float, 0> { static constexpr int BK = 16; };
 template <> struct GemmCfg<float, 1> { static constexpr int BK = 32; };
 template <> struct GemmCfg<float, 2> { static constexpr int BK = 32; };
 
+// Tiles of a launch; lower (m >= n): only tiles with tile_m >= tile_n, the triangle of the top
+// tiles_n tile rows and the full tile rows below it.
+__host__ __device__ __forceinline__ int tile_count(int tiles_m, int tiles_n, int lower) {
+  return lower ? tiles_n * (tiles_n + 1) / 2 + (tiles_m - tiles_n) * tiles_n : tiles_m * tiles_n;
+}
+
 // Map a linear workgroup id to a (tile_m, tile_n) pair.
-// lower: enumerate tiles with tile_m >= tile_n only (m == n).
 __device__ __forceinline__ void tile_coords(int w, int tiles_m, int tiles_n, int lower, int& tm, int& tn) {
-  int total = lower ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
+  int total = tile_count(tiles_m, tiles_n, lower);
   // XCD-aware remap: workgroup w runs on XCD (w % 8).  Give each XCD a
   // contiguous range of tile ids so that its L2 sees neighbouring tiles.
   int per = total / 8;
@@ -59,13 +64,18 @@ __device__ __forceinline__ void tile_coords(int w, int tiles_m, int tiles_n, int
     const int rows = min(GM, tiles_m - band * GM);
     tm = band * GM + r % rows;
     tn = r / rows;
-  } else {
+  } else if (t < tiles_n * (tiles_n + 1) / 2) {
     // t -> (tm, tn) with tm >= tn, rows of the lower triangle of tiles
     int r = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
     while ((r + 1) * (r + 2) / 2 <= t) ++r;
     while (r * (r + 1) / 2 > t) --r;
     tm = r;
     tn = t - r * (r + 1) / 2;
+  } else {
+    // the full tile rows below the triangle (m > n)
+    const int q = t - tiles_n * (tiles_n + 1) / 2;
+    tm = tiles_n + q / tiles_n;
+    tn = q - (q / tiles_n) * tiles_n;
   }
 }
 
@@ -483,8 +493,9 @@ gemm_mixed_kernel(GemmArgs<float> g) {
 template <typename T>
 hipError_t launch_gemm(const GemmArgs<T>& g, int batch, int mode, hipStream_t s) {
   if (g.m <= 0 || g.n <= 0 || g.k <= 0 || batch <= 0) return hipSuccess;
+  if (g.lower && g.m < g.n) return hipErrorInvalidValue;
   int tiles_m = (g.m + BM - 1) / BM, tiles_n = (g.n + BN - 1) / BN;
-  int tiles = g.lower ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
+  int tiles = tile_count(tiles_m, tiles_n, g.lower);
   dim3 grid(tiles, batch);
   // 16-byte loads need 16-byte aligned bases and leading dimensions that keep every column aligned
   constexpr int nv = 16 / (int)sizeof(T);
@@ -493,7 +504,7 @@ hipError_t launch_gemm(const GemmArgs<T>& g, int batch, int mode, hipStream_t s)
   if (mode == 0) {
     if (tiles < 2 * 256) {
       const int tm64 = (g.m + 63) / 64, tn64 = (g.n + 63) / 64;
-      const dim3 grid64(g.lower ? tm64 * (tm64 + 1) / 2 : tm64 * tn64, batch);
+      const dim3 grid64(tile_count(tm64, tn64, g.lower), batch);
       if (vec)
         hipLaunchKernelGGL((gemm_native_kernel<T, true, 64>), grid64, dim3(NT), 0, s, g);
       else

@@ -12,7 +12,7 @@ namespace cds {
 // C += alpha * A * op(B); A m x k, op(B) k x n, all column-major.  The native-precision
 // kernel applies alpha to A (exact for the alpha = -1 of every caller).
 // transB = 1: op(B) = B^T with B stored n x k (ldb).
-// lower = 1: only C(i, j) with i >= j is computed and written (m == n).
+// lower = 1 (m >= n): only C(i, j) with i >= j is computed and written.
 // For the FP16 operand mode, op(B) is multiplied before rounding by the power of
 // two 2^e that brings max|op(B)| to [2^13, 2^14) (|e| <= 100), and the product by
 // 2^-e; max|op(B)| comes as kScaleParts partial maxima per matrix (scale_part,
