@@ -258,21 +258,25 @@ __device__ __forceinline__ void colstep_exchange(uint64_t* slots, const SlotLayo
 // back through the interchanges in reverse order, so there is no serial table
 // update.  Wave 0 only; returns the entry count in every lane.
 template <int W>
-__device__ int compose_leaf(const int* s_piv, int c0, int wl, int* s_dst, int* s_src, int* s_ne) {
+__device__ __forceinline__ int compose_leaf(const int* s_piv, int c0, int wl, int* s_dst, int* s_src, int* s_ne) {
   const int lane = lane_id();
   const int c1 = c0 + wl;
   const int mypiv = lane < wl ? s_piv[lane] : -1;
   // lane cc names the pivot row of column cc when it lies below the leaf and no earlier column chose it
+  // (straight-line code over all W lanes: lanes at or beyond wl hold -1, which no valid lane holds)
   bool other = mypiv >= c1;
-  for (int cc = 0; cc < wl; ++cc) {
+#pragma unroll
+  for (int cc = 0; cc < W; ++cc) {
     const int pc = __builtin_amdgcn_readlane(mypiv, cc);
     other = other && !(cc < lane && pc == mypiv);
   }
   int src = c0 + lane, osrc = mypiv;
-  for (int cc = wl - 1; cc >= 0; --cc) {
+#pragma unroll
+  for (int cc = W - 1; cc >= 0; --cc) {
     const int a = c0 + cc, b = __builtin_amdgcn_readlane(mypiv, cc);
-    src = src == a ? b : (src == b ? a : src);
-    osrc = osrc == a ? b : (osrc == b ? a : osrc);
+    const bool on = cc < wl;
+    src = on ? (src == a ? b : (src == b ? a : src)) : src;
+    osrc = on ? (osrc == a ? b : (osrc == b ? a : osrc)) : osrc;
   }
   if (lane < wl) {
     s_dst[lane] = c0 + lane;
@@ -291,7 +295,7 @@ __device__ int compose_leaf(const int* s_piv, int c0, int wl, int* s_dst, int* s
 
 // Compact the entries of a leaf's move list whose source (src_side) or
 // destination row lies in this workgroup's rows.  Wave 0 only; ne <= 3W <= 128.
-__device__ void compact_entries(const int* s_dst, const int* s_src, int ne, int g, int* s_own, int* s_nown,
+__device__ __forceinline__ void compact_entries(const int* s_dst, const int* s_src, int ne, int g, int* s_own, int* s_nown,
                                 int* s_dl, int* s_ndl) {
   const int lane = lane_id();
   int no = 0, nd = 0;
@@ -432,11 +436,19 @@ __global__ void __launch_bounds__(PNT, 2) panel_kernel(PanelArgs<T> P) {
         if (g == 0 && piv == (T)0) atomicCAS(P.info + b, 0, P.k + j + 1);
       }
     }
-    // the leaf's final values (up to later interchanges) and the MFMA operand copy
+    // the leaf's final values (up to later interchanges) and the MFMA operand copy: a wave-uniform
+    // column base and one 32-bit row offset for every column, so that no store waits for the one
+    // before it to release an address register
     if (act) {
+      const uint32_t urow = (uint32_t)row;
+      if (wl == W) {
 #pragma unroll
-      for (int cc = 0; cc < W; ++cc)
-        if (cc < wl) A[row + (size_t)(c0 + cc) * lda] = v.get(cc);
+        for (int cc = 0; cc < W; ++cc) (A + (size_t)(c0 + cc) * lda)[urow] = v.get(cc);
+      } else {
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc)
+          if (cc < wl) (A + (size_t)(c0 + cc) * lda)[urow] = v.get(cc);
+      }
     }
     // these two barriers order LDS only (the pivots, L11 and the move lists); nothing reads the
     // leaf columns just stored before the full barriers further down
