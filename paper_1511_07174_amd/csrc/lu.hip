@@ -380,6 +380,7 @@ __global__ void __launch_bounds__(PNT, 2) panel_kernel(PanelArgs<T> P) {
   __shared__ int s_own[3 * W], s_dl[3 * W];
   __shared__ int s_ne, s_nown, s_ndl;
   __shared__ T Ubuf[W][PCH + 8];
+  __shared__ double Li2[2][16][17];   // inverses of L11's two unit-lower 16 x 16 diagonal blocks
 
   int leafc = 0;
   for (int c0 = 0; c0 < jb; c0 += W, ++leafc) {
@@ -458,6 +459,21 @@ __global__ void __launch_bounds__(PNT, 2) panel_kernel(PanelArgs<T> P) {
       // the lists written by other lanes of this wave are read below: order the LDS accesses
       wave_fence();
       compact_entries(s_dst, s_src, ne0, g, s_own, &s_nown, s_dl, &s_ndl);
+    } else if (F64 && wave == 1 && lane < 32) {
+      // meanwhile (FP64 panels): lane c, column c % 16 of the inverse of L11's unit-lower diagonal
+      // block c / 16, by forward substitution (the terms q < c multiply y[q] = 0); rows at or beyond
+      // wl act as the identity
+      const int bb = lane >> 4, c = lane & 15, r0 = 16 * bb;
+      double y[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        double sacc = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < i; ++q) sacc -= (double)L11[r0 + i][r0 + q] * y[q];
+        y[i] = r0 + i >= wl ? ((i == c) ? 1.0 : 0.0) : (i < c ? 0.0 : sacc);
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Li2[bb][i][c] = y[i];
     }
     lds_barrier();
     if (g == 0 && tid < wl) ipiv[c0 + tid] = P.k + s_piv[tid] + 1;
@@ -563,10 +579,47 @@ __global__ void __launch_bounds__(PNT, 2) panel_kernel(PanelArgs<T> P) {
       }
       __syncthreads();
       if (cw == 0) break;
-      // U_right = L11^{-1} P_top, one thread per column, by columns of L11: as soon as u[t] is final
-      // it is taken out of every later row, so each u[i] still subtracts L11[i][t] u[t] in the order
-      // t = 0, 1, ..., i - 1, while the dependent chain is W steps long instead of W^2 / 2
-      if (tid < cw) {
+      // U_right = L11^{-1} P_top.  FP64: on MFMA tiles of 16 columns (wave w: tiles w, w + 4, ...), by
+      // 16 x 16 blocks: X0 = inv(L00) P0, P1 -= L10 X0, X1 = inv(L11) P1 (products exact on small
+      // dyadic data, as in the TRSM).  Accumulator v of a product holds row k64(v) of column l % 16,
+      // and every product takes its k index so that the previous product's accumulators are its B
+      // operand.  FP32 (where the extra registers slowed the column loop more than this saves): one
+      // thread per column, by columns of L11: as soon as u[t] is final it is taken out of every
+      // later row, so each u[i] still subtracts L11[i][t] u[t] in the order t = 0, 1, ..., i - 1,
+      // while the dependent chain is W steps long instead of W^2 / 2.
+      if constexpr (F64) {
+        const int li = lane & 15, kl = lane >> 4;
+        auto k64 = [&](int v) { return kl + 4 * v; };
+        auto kout = [&](int v) { return F64 ? kl + 4 * v : 4 * kl + v; };
+        for (int ct = wave; 16 * ct < cw; ct += 4) {
+          const int cx = 16 * ct + li;   // column of the chunk
+          d4 x0 = {0.0, 0.0, 0.0, 0.0}, x1 = {0.0, 0.0, 0.0, 0.0};
+          acc_t p1;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) p1[v] = 16 + kout(v) < wl ? Ubuf[16 + kout(v)][cx] : (T)0;
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int k = k64(s);
+            x0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Li2[0][li][k], k < wl ? (double)Ubuf[k][cx] : 0.0, x0, 0, 0, 0);
+          }
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const T a = 16 + li < wl ? -L11[16 + li][k64(s)] : (T)0;
+            if constexpr (F64)
+              p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, x0[s], p1, 0, 0, 0);
+            else
+              p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, (T)x0[s], p1, 0, 0, 0);
+          }
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            x1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Li2[1][li][kout(s)], (double)p1[s], x1, 0, 0, 0);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            Ubuf[k64(v)][cx] = (T)x0[v];
+            Ubuf[16 + k64(v)][cx] = (T)x1[v];
+          }
+        }
+      } else if (tid < cw) {
         T u[W];
 #pragma unroll
         for (int i = 0; i < W; ++i) u[i] = (i < wl) ? Ubuf[i][tid] : (T)0;
