@@ -257,26 +257,41 @@ __device__ __forceinline__ void colstep_exchange(uint64_t* slots, const SlotLayo
 // leaf, each once, in the order of first use).  Every lane traces its position
 // back through the interchanges in reverse order, so there is no serial table
 // update.  Wave 0 only; returns the entry count in every lane.
-template <int W>
-__device__ __forceinline__ int compose_leaf(const int* s_piv, int c0, int wl, int* s_dst, int* s_src, int* s_ne) {
+template <int W, bool FULL>
+__device__ __forceinline__ int compose_leaf(const int* s_piv, int c0, int wl_, int* s_dst, int* s_src, int* s_ne) {
+  const int wl = FULL ? W : wl_;   // FULL: a whole leaf, so that no column needs a bounds mask
   const int lane = lane_id();
   const int c1 = c0 + wl;
   const int mypiv = lane < wl ? s_piv[lane] : -1;
-  // lane cc names the pivot row of column cc when it lies below the leaf and no earlier column chose it
-  // (straight-line code over all W lanes: lanes at or beyond wl hold -1, which no valid lane holds)
+  // lane cc names the pivot row of column cc when it lies below the leaf and no earlier column chose it.
+  // The pivots come from LDS four at a time (every lane reads the same words), entries at or beyond
+  // wl (left from an earlier leaf) read as -1, which no valid lane holds.
+  const int4* pv4 = reinterpret_cast<const int4*>(s_piv);
   bool other = mypiv >= c1;
 #pragma unroll
-  for (int cc = 0; cc < W; ++cc) {
-    const int pc = __builtin_amdgcn_readlane(mypiv, cc);
-    other = other && !(cc < lane && pc == mypiv);
+  for (int q = 0; q < W / 4; ++q) {
+    const int4 pv = pv4[q];
+    const int pcs[4] = {pv.x, pv.y, pv.z, pv.w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int cc = 4 * q + u;
+      const int pc = cc < wl ? pcs[u] : -1;
+      other = other && !(cc < lane && pc == mypiv);
+    }
   }
   int src = c0 + lane, osrc = mypiv;
 #pragma unroll
-  for (int cc = W - 1; cc >= 0; --cc) {
-    const int a = c0 + cc, b = __builtin_amdgcn_readlane(mypiv, cc);
-    const bool on = cc < wl;
-    src = on ? (src == a ? b : (src == b ? a : src)) : src;
-    osrc = on ? (osrc == a ? b : (osrc == b ? a : osrc)) : osrc;
+  for (int q = W / 4 - 1; q >= 0; --q) {
+    const int4 pv = pv4[q];
+    const int pcs[4] = {pv.x, pv.y, pv.z, pv.w};
+#pragma unroll
+    for (int u = 3; u >= 0; --u) {
+      const int cc = 4 * q + u;
+      const int a = c0 + cc, b = pcs[u];
+      const bool on = cc < wl;
+      src = on ? (src == a ? b : (src == b ? a : src)) : src;
+      osrc = on ? (osrc == a ? b : (osrc == b ? a : osrc)) : osrc;
+    }
   }
   if (lane < wl) {
     s_dst[lane] = c0 + lane;
@@ -375,7 +390,7 @@ __global__ void __launch_bounds__(PNT, 2) panel_kernel(PanelArgs<T> P) {
   __shared__ T jrow[W];
   __shared__ int s_p;
   __shared__ T L11[W][W + 1];
-  __shared__ int s_piv[W];
+  __shared__ __align__(16) int s_piv[W];
   __shared__ int s_dst[3 * W], s_src[3 * W];
   __shared__ int s_own[3 * W], s_dl[3 * W];
   __shared__ int s_ne, s_nown, s_ndl;
@@ -455,7 +470,8 @@ __global__ void __launch_bounds__(PNT, 2) panel_kernel(PanelArgs<T> P) {
     // leaf columns just stored before the full barriers further down
     lds_barrier();
     if (wave == 0) {
-      const int ne0 = compose_leaf<W>(s_piv, c0, wl, s_dst, s_src, &s_ne);
+      const int ne0 = wl == W ? compose_leaf<W, true>(s_piv, c0, wl, s_dst, s_src, &s_ne)
+                              : compose_leaf<W, false>(s_piv, c0, wl, s_dst, s_src, &s_ne);
       // the lists written by other lanes of this wave are read below: order the LDS accesses
       wave_fence();
       compact_entries(s_dst, s_src, ne0, g, s_own, &s_nown, s_dl, &s_ndl);
