@@ -116,7 +116,7 @@ __device__ __forceinline__ T lane_get(T v, int l) {
 }
 
 // Column c of the inverse of the lower-triangular 16 x 16 block at (r0, r0) of the LDS block
-// (ld PLD), in FP64, by forward substitution: the same operations as diag_inv16_column, as
+// (leading dimension LD), in FP64, by forward substitution: the same operations as diag_inv16_column, as
 // straight-line code (the terms q < c multiply y[q] = 0 and leave the sum as it is).  EDGE: rows
 // at or beyond jb act as the identity (they read row jb - 1, and the result is replaced).
 template <typename T, bool EDGE, int LD>
