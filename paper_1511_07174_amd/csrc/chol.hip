@@ -408,8 +408,11 @@ cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int
       KScope ks(c.timer, CDS_KC_TRSM, st, (double)jb * jb * rem, 0.0);
       if (jb > PJB && launch_diag_inv16<T>(A + k + (size_t)k * lda, lda, 0, jb, 0, linv, 0, 1, st) != hipSuccess)
         return CDS_HIP_ERROR;
+      // the staged 16-column slices (L11 and its inverses in LDS) for every size: shorter here than
+      // 32-column slices that read L11 from memory, both at the end (on the critical path) and beside
+      // a large rest update
       if (launch_trsm16<T>(A + k + (size_t)k * lda, lda, 0, linv, 0, A + (k + jb) + (size_t)k * lda, lda, 0, jb, rem,
-                           1, 1, info, st) != hipSuccess)
+                           1, 1, info, st, 1 << 30) != hipSuccess)
         return CDS_HIP_ERROR;
     }
     if (mode == 2 && scale_part != nullptr) {

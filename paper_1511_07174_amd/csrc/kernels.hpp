@@ -77,6 +77,7 @@ constexpr size_t kErrRegion = 256;
 // Blocked triangular solve X = L^{-1} B (jb x jb lower L, unit or not) on MFMA tiles, from the
 // FP64 inverses of L's 16 x 16 diagonal blocks (launch_diag_inv16, trsm16_inv_elems(jb) doubles
 // per matrix).  trans = 1: B element (r, c) stored at B[c + r * ldb].  guard: skip when *guard != 0.
+// Calls with at most narrow_cols columns in all take 16-column slices (staging L11 in LDS).
 size_t trsm16_inv_elems(int jb);
 template <typename T>
 hipError_t launch_diag_inv16(const T* L, int64_t lda, int64_t strideA, int jb, int unit, double* Linv,
@@ -84,7 +85,7 @@ hipError_t launch_diag_inv16(const T* L, int64_t lda, int64_t strideA, int jb, i
 template <typename T>
 hipError_t launch_trsm16(const T* L, int64_t lda, int64_t strideA, const double* Linv, int64_t strideI, T* B,
                          int64_t ldb, int64_t strideB, int jb, int ncols, int trans, int batch, const int32_t* guard,
-                         hipStream_t s);
+                         hipStream_t s, int narrow_cols = 1024);
 size_t getrf_ws_bytes(int n, int nb, int leaf, int batch, size_t elem);
 size_t getrs_ws_bytes(int n, int nrhs, int batch, size_t elem);
 size_t potrf_ws_bytes(int n, int nb, size_t elem);

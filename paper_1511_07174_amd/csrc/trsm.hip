@@ -305,14 +305,14 @@ hipError_t launch_diag_inv16(const T* L, int64_t lda, int64_t strideA, int jb, i
 template <typename T>
 hipError_t launch_trsm16(const T* L, int64_t lda, int64_t strideA, const double* Linv, int64_t strideI, T* B,
                          int64_t ldb, int64_t strideB, int jb, int ncols, int trans, int batch, const int32_t* guard,
-                         hipStream_t s) {
+                         hipStream_t s, int narrow_cols) {
   if (jb <= 0 || ncols <= 0 || batch <= 0) return hipSuccess;
   const int nblk = (jb + 15) / 16;
   // at most 512 rows: 4 waves x 8 groups of 16
   if (jb > 512) return hipErrorInvalidValue;
   // narrow calls (a look-ahead's next panel) take 16-column slices: twice the workgroups on a
   // dependency chain whose length does not shrink with the width
-  const bool narrow = (int64_t)batch * ncols <= 1024;
+  const bool narrow = (int64_t)batch * ncols <= narrow_cols;
   auto go = [&](auto kern, int tcw, bool stage) {
     const size_t sm = stage ? trsm16_stage_bytes(nblk, tcw, sizeof(T)) : (size_t)nblk * 16 * (tcw + 1) * sizeof(T);
     const dim3 grid((ncols + tcw - 1) / tcw, batch);
@@ -341,8 +341,8 @@ template hipError_t launch_diag_inv16<double>(const double*, int64_t, int64_t, i
 template hipError_t launch_diag_inv16<float>(const float*, int64_t, int64_t, int, int, double*, int64_t, int,
                                              hipStream_t);
 template hipError_t launch_trsm16<double>(const double*, int64_t, int64_t, const double*, int64_t, double*, int64_t,
-                                          int64_t, int, int, int, int, const int32_t*, hipStream_t);
+                                          int64_t, int, int, int, int, const int32_t*, hipStream_t, int);
 template hipError_t launch_trsm16<float>(const float*, int64_t, int64_t, const double*, int64_t, float*, int64_t,
-                                         int64_t, int, int, int, int, const int32_t*, hipStream_t);
+                                         int64_t, int, int, int, int, const int32_t*, hipStream_t, int);
 
 }  // namespace cds
