@@ -181,7 +181,7 @@ cds_status_t cds_dgetrs_strided_batched(cds_handle_t handle, cds_op_t op, int64_
                                         double* B, int64_t ldb, int64_t strideB, int64_t batch);
 
 /* ---------------------------------------------------------------------------
- * Cholesky (Sec. 2: "In the case of SPD matrices, we have A = LL^t"), lower.
+ * Cholesky A = L L^T of an SPD matrix (Sec. 2), lower.
  *   A (n x n, lda): in the SPD matrix (lower triangle read); out L in the lower
  *   triangle.  The strict upper triangle is never read or written.
  *   info: 0, or k > 0 if the leading minor of order k is not positive

@@ -7,12 +7,12 @@
  * the test suite, the smoke check and the benchmark's CPU-baseline leg load
  * it.  It shares no code, header or constant with the HIP library.
  *
- * What it computes (Sec. 2 of the paper, "Serial iterative and direct
- * methods"): the direct method for Ax = b in two steps, (1) factor A = LU with
+ * What it computes (Sec. 2 of the paper, on the serial iterative and direct
+ * methods): the direct method for Ax = b in two steps, (1) factor A = LU with
  * L unit lower triangular and partial pivoting (the textbook algorithm the
  * paper cites from Golub & Van Loan), or A = L L^T for SPD A, then (2) the two
- * triangular solves Ly = b and Ux = y.  Blocked right-looking LU ("delayed
- * updating", Sec. 2 last paragraph) is a reordering of exactly these
+ * triangular solves Ly = b and Ux = y.  Blocked right-looking LU (delayed
+ * updating, Sec. 2 last paragraph) is a reordering of exactly these
  * operations, so the oracle is the unblocked definition, one column at a time.
  *
  * Conventions (readings where the paper is silent): column-major storage with

@@ -1,5 +1,5 @@
-// Blocked right-looking Cholesky A = L L^T (Sec. 2: "In the case of SPD
-// matrices, we have A = LL^t"), lower triangle only.
+// Blocked right-looking Cholesky A = L L^T of an SPD matrix (Sec. 2), lower
+// triangle only.
 //   potf2_lds_kernel / potf2_kernel   one workgroup factors the jb x jb
 //                  diagonal block in 32-wide sub-blocks (held in LDS for jb <= 128);
 //                  the first non-positive (or NaN) pivot records info and stops the

@@ -1,6 +1,6 @@
 // Trailing-matrix update  C += alpha * A * op(B)  on MFMA (gfx950).
 //
-// This is the rank-k "delayed update" of blocked LU (A22 -= L21 U12) and, in
+// This is the delayed rank-k update of blocked LU (A22 -= L21 U12) and, in
 // lower-tile mode, the symmetric update of blocked Cholesky (A22 -= L21 L21^T):
 // Sec. 2 of the paper, where k rank-1 updates are replaced by one rank-k update
 // (level-3 BLAS).  It carries ~all of the O(n^3) flops.

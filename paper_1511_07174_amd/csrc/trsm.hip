@@ -1,6 +1,6 @@
 // Triangular solve with many right-hand sides against a jb x jb lower triangle
 // (the U12 = L11^{-1} A12 step of the blocked LU, and L21 = A21 L11^{-T} of the
-// blocked Cholesky, Sec. 2: the rank-k "delayed update" needs these blocks).
+// blocked Cholesky, Sec. 2: the delayed rank-k update needs these blocks).
 //
 //   diag_inv16_kernel  inverts the 16 x 16 diagonal blocks of L11 (unit or not)
 //                      by substitution, one column of an inverse per thread.
