@@ -141,9 +141,9 @@ __device__ __forceinline__ void inv16_column_ld(const T* Ds, int r0, int jb, int
   }
 }
 
-// jb <= 128: the whole diagonal block lives in LDS (column-major, ld 130 for FP64 and
-// 132 for FP32, so that every column starts on 16 bytes) for the duration of the
-// kernel; its columns arrive by direct global-to-LDS loads (the upper triangle comes
+// jb <= 128 (FP64) or 192 (FP32): the whole diagonal block lives in LDS (column-major,
+// ld jb_max + 2 for FP64 and + 4 for FP32, so that every column starts on 16 bytes) for the
+// duration of the kernel; its columns arrive by direct global-to-LDS loads (the upper triangle comes
 // along and is never read) and the lower triangle is written back once.  Per 32-wide sub-block:
 //   (a) one wave factors the sub-block's diagonal with row r in lane r (registers).
 //       The entries of column j that the later columns need come from the other
@@ -155,13 +155,15 @@ __device__ __forceinline__ void inv16_column_ld(const T* Ds, int r0, int jb, int
 //       MFMA tiles: X0 = B0 inv(L00)^T, B1 -= X0 L10^T, X1 = B1 inv(L11)^T;
 //   (c) the rest of the block gets the symmetric rank-32 update on MFMA tiles.
 // The 16 x 16 inverses are also the ones the TRSM below the block uses.
-constexpr int PJB = 128;
+// the largest diagonal block held in LDS
+template <typename T> constexpr int pjb() { return sizeof(T) == 8 ? 128 : 192; }
 
 template <typename T>
 __global__ void __launch_bounds__(256) potf2_lds_kernel(T* A, int64_t lda, int k, int jb, int32_t* info,
                                                         double* linv) {
   constexpr bool F64 = std::is_same<T, double>::value;
   typedef typename std::conditional<F64, d4, f4>::type acc_t;
+  constexpr int PJB = pjb<T>();
   constexpr int PLD = PJB + (F64 ? 2 : 4);
   __shared__ __align__(16) T Ds[PJB * PLD];   // (r, c) at Ds[c * PLD + r]
   __shared__ double Iv[2][16][17];   // inverses of the sub-block's 16 x 16 diagonal blocks, (i, c) at Iv[b][i][c]
@@ -392,7 +394,7 @@ cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int
   auto panel = [&](int k, int jb, int par, hipStream_t st) -> cds_status_t {
     {
       KScope ks(c.timer, CDS_KC_PANEL, st, (double)jb * jb * jb / 3.0, (double)jb * jb * sizeof(T));
-      if (jb <= PJB) {
+      if (jb <= pjb<T>()) {
         hipLaunchKernelGGL((potf2_lds_kernel<T>), dim3(1), dim3(256), 0, st, A, lda, k, jb, info,
                            n - k - jb > 0 ? linv : nullptr);
       } else {
@@ -406,7 +408,7 @@ cds_status_t potrf_run_mode(Ctx& c, int n, T* A, int64_t lda, int32_t* info, int
     {
       // L21 = A21 L11^{-T}: the transposed column solve L11 L21^T = A21^T on MFMA tiles
       KScope ks(c.timer, CDS_KC_TRSM, st, (double)jb * jb * rem, 0.0);
-      if (jb > PJB && launch_diag_inv16<T>(A + k + (size_t)k * lda, lda, 0, jb, 0, linv, 0, 1, st) != hipSuccess)
+      if (jb > pjb<T>() && launch_diag_inv16<T>(A + k + (size_t)k * lda, lda, 0, jb, 0, linv, 0, 1, st) != hipSuccess)
         return CDS_HIP_ERROR;
       // the staged 16-column slices (L11 and its inverses in LDS) for every size: shorter here than
       // 32-column slices that read L11 from memory, both at the end (on the critical path) and beside

@@ -302,6 +302,35 @@ def test_posv_mixed(cds, prec):
     assert oracle.eta_inf(A, host(Xd), B) <= 1e-14
 
 
+@pytest.mark.parametrize("nb", [128, 160, 192])
+def test_spotrf_block_sizes(cds, nb):
+    """FP32 Cholesky with the diagonal block in LDS up to 192 columns (FP32 only): the factor of the
+    FP32-rounded matrix has a backward error of a few FP32 units (the bound of the FP64 test, in
+    FP32's epsilon), agrees with the oracle's factor to FP32 accuracy, and the mixed solves (FP32
+    and FP16-operand factors) with the same block size converge to the FP64 bar."""
+    from paper_1511_07174_amd.cds import OPT_NB
+    n = 700
+    A = synth.spd_matrix(n, 12)
+    A32 = A.astype(np.float32).astype(np.float64)
+    B = synth.rng(13).uniform(-1, 1, (n, 2))
+    h = cds.handle()
+    h.set_option(OPT_NB, nb)
+    try:
+        L, info = cds.potrf(to_dev(A32, torch.float32))
+        sols = [cds.solve(to_dev(A), to_dev(B), precision=p, spd=True) for p in ("fp32", "fp16")]
+    finally:
+        h.set_option(OPT_NB, 0)
+    Lh = np.tril(host(L).astype(np.float64))
+    Lo, info_o = oracle.potrf(A32)
+    assert int(info.item()) == 0 and info_o == 0
+    assert oracle.rho_llt(A32, Lh, eps=EPS32) <= 30
+    assert np.max(np.abs(Lh - np.tril(Lo))) <= 1e3 * EPS32 * np.max(np.abs(np.tril(Lo)))
+    for Xd, res in sols:
+        assert res[0].converged, res[0]
+        assert oracle.eta_inf(A, host(Xd), B) <= 1e-14
+    no_device_error(cds)
+
+
 @pytest.mark.parametrize("spd", [False, True])
 def test_fp16_operand_scale_is_exact(cds, spd):
     """The FP16 update multiplies op(B) by a power of two taken from max|op(B)| and the product by its
