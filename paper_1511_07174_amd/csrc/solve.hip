@@ -621,7 +621,6 @@ __global__ void __launch_bounds__(TNT, 1) trsv1_binv_kernel(BinvArgs a) {
   const int row = (q & 1) * 64 + lane;    // row of the block
   __shared__ int s_ticket;
   __shared__ float sD[BB][BB];            // D^{-1}: element (i, t) at [t][i]
-  __shared__ float sK[BB][BB];            // K, the same layout
   __shared__ float sv[BB];
   __shared__ float red[2][BB];
   __shared__ float red2[2][BB];
@@ -639,8 +638,6 @@ __global__ void __launch_bounds__(TNT, 1) trsv1_binv_kernel(BinvArgs a) {
 
   // independent of every other block: D^{-1} and K to LDS, the right-hand side
   for (int e = tid; e < BB * BB; e += TNT) (&sD[0][0])[e] = Pb[e];
-  if (ndep > 0)
-    for (int e = tid; e < BB * BB; e += TNT) (&sK[0][0])[e] = Pb[BB * BB + e];
   const float rhs = (ch == 0 && rok) ? Y[r0 + row] : 0.f;
 
   float mbuf[DEPTH][64];
@@ -695,6 +692,14 @@ __global__ void __launch_bounds__(TNT, 1) trsv1_binv_kernel(BinvArgs a) {
       }
     }
   }
+  // this thread's 64 entries of K (row `row`, the wave's half of the columns; element (i, t) at
+  // t BB + i), held in registers for the chain step, loaded while D^{-1} v is formed
+  float kreg[64];
+  if (ndep > 0) {
+    const float* Kp = Pb + BB * BB + (size_t)(ch * 64) * BB + row;
+#pragma unroll
+    for (int t = 0; t < 64; ++t) kreg[t] = Kp[(size_t)t * BB];
+  }
   // v = r - (products so far), then c = D^{-1} v
   red[ch][row] = acc0 + acc1;
   __syncthreads();
@@ -724,10 +729,10 @@ __global__ void __launch_bounds__(TNT, 1) trsv1_binv_kernel(BinvArgs a) {
 #pragma unroll
     for (int t = 0; t < 64; t += 4) {
       const f4 yv = *reinterpret_cast<const f4*>(&sy[q][t]);
-      p0 = fmaf(sK[ch * 64 + t][row], yv[0], p0);
-      p1 = fmaf(sK[ch * 64 + t + 1][row], yv[1], p1);
-      p2 = fmaf(sK[ch * 64 + t + 2][row], yv[2], p2);
-      p3 = fmaf(sK[ch * 64 + t + 3][row], yv[3], p3);
+      p0 = fmaf(kreg[t], yv[0], p0);
+      p1 = fmaf(kreg[t + 1], yv[1], p1);
+      p2 = fmaf(kreg[t + 2], yv[2], p2);
+      p3 = fmaf(kreg[t + 3], yv[3], p3);
     }
     red2[ch][row] = (p0 + p1) + (p2 + p3);
     __syncthreads();
