@@ -64,8 +64,8 @@ typedef enum { CDS_PREC_FP32 = 0, CDS_PREC_BF16 = 1, CDS_PREC_FP16 = 2 } cds_pre
 typedef enum {
   CDS_OPT_NB = 0,           /* block size override for getrf/potrf (0 = tuning table / default) */
   CDS_OPT_LOOKAHEAD = 1,    /* 1 (default): overlap the next panel with the trailing update */
-  CDS_OPT_LEAF = 2,         /* panel leaf width (0 = default) */
-  CDS_OPT_PANEL_WGS = 3,    /* max workgroups of the panel kernel (0 = default) */
+  CDS_OPT_LEAF = 2,         /* panel leaf width: 0 (default) or 32, the one width the panel is built for */
+  CDS_OPT_PANEL_WGS = 3,    /* reserved: 0 only (the panel runs one workgroup per 256 of its rows) */
   CDS_OPT_KERNEL_TIMING = 4 /* 1: record a pair of events around every launch of the kernel classes
                                below, on the stream the kernel runs on (see cds_kernel_timing) */
 } cds_option_t;

@@ -28,7 +28,7 @@ struct cds_handle_s {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   void* ws = nullptr;
   size_t ws_bytes = 0;
-  int nb_override = 0, lookahead = 1, leaf = 0, panel_wgs = 0, timing = 0;
+  int nb_override = 0, lookahead = 1, leaf = 0, timing = 0;
   std::vector<TuneEntry> tune;
   cds::KTimer timer;
   void* noalloc_err = nullptr;   // error word of the fixed scratch, once a no-allocation call has used it
@@ -72,7 +72,6 @@ Ctx make_ctx(cds_handle_s* h) {
   c.nb_override = h->nb_override;
   c.lookahead = h->lookahead;
   c.leaf = h->leaf;
-  c.panel_wgs = h->panel_wgs;
   c.timer = h->timing ? &h->timer : nullptr;
   return c;
 }
@@ -337,9 +336,7 @@ cds_status_t cds_set_option(cds_handle_t h, cds_option_t opt, int64_t v) {
       h->leaf = (int)v;
       return CDS_SUCCESS;
     case CDS_OPT_PANEL_WGS:
-      if (v < 0) return CDS_INVALID_VALUE;
-      h->panel_wgs = (int)v;
-      return CDS_SUCCESS;
+      return v == 0 ? CDS_SUCCESS : CDS_INVALID_VALUE;
     case CDS_OPT_KERNEL_TIMING:
       if (v != 0 && v != 1) return CDS_INVALID_VALUE;
       h->timing = (int)v;

@@ -68,7 +68,6 @@ struct Ctx {
   int nb_override;
   int lookahead;
   int leaf;
-  int panel_wgs;
   KTimer* timer;           // null unless kernel timing is on
 };
 
